@@ -1,0 +1,137 @@
+"""ctypes binding of the FP64 CPU oracle.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports it.
+
+Arrays are numpy float64 / complex128, C-contiguous; a real field set is
+shaped (8, n, n, n) with axes (field, z, y, x) and field order
+rho, m_x, m_y, m_z, B_x, B_y, B_z, E.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DIAG_NAMES = (
+    "mass", "mom_x", "mom_y", "mom_z", "e_kin", "e_mag", "e_int", "e_tot",
+    "h_cross", "h_mag", "divb_rms", "divb_max", "divb_rel", "dt_cfl", "c_s",
+    "v_a", "mach_s", "mach_a", "nonfinite", "j_rms",
+)
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("gamma", ctypes.c_double),
+        ("nu", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+def build() -> str:
+    """Compile liboracle.so in place (gcc, OpenMP)."""
+    subprocess.run(["make", "-s", "-C", _HERE, "-B", "liboracle.so"], check=True)
+    return _LIBPATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            build()
+        L = ctypes.CDLL(_LIBPATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_fft1d.argtypes = [ctypes.c_int32, dp, dp, ctypes.c_int32]
+        L.orc_fft3d.argtypes = [ctypes.c_int32, dp, ctypes.c_int32]
+        L.orc_project.argtypes = [ctypes.c_int32, dp]
+        L.orc_rhs.argtypes = [ctypes.POINTER(_Params), dp, dp]
+        L.orc_run.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_int32]
+        L.orc_diag.argtypes = [ctypes.POINTER(_Params), dp, dp]
+        L.orc_neumaier_sum.argtypes = [dp, ctypes.c_int64]
+        L.orc_neumaier_sum.restype = ctypes.c_double
+        L.orc_num_threads.restype = ctypes.c_int32
+        for name in ("orc_fft1d", "orc_fft3d", "orc_project", "orc_rhs", "orc_run", "orc_diag"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def _params(n, gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=0.0, cfl=0.1) -> _Params:
+    return _Params(int(n), float(gamma), float(nu), float(eta), float(dt), float(cfl))
+
+
+def fft1d(x, sign: int = -1) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.empty_like(x)
+    _check(lib().orc_fft1d(x.size, _ptr(x.view(np.float64)), _ptr(out.view(np.float64)), sign), "fft1d")
+    return out
+
+
+def fft3d(a, sign: int = -1) -> np.ndarray:
+    a = np.array(a, dtype=np.complex128, order="C", copy=True)
+    n = a.shape[0]
+    assert a.shape == (n, n, n)
+    _check(lib().orc_fft3d(n, _ptr(a.view(np.float64)), sign), "fft3d")
+    return a
+
+
+def project(f) -> np.ndarray:
+    f = np.array(f, dtype=np.float64, order="C", copy=True)
+    _check(lib().orc_project(f.shape[0], _ptr(f)), "project")
+    return f
+
+
+def _fields(U) -> np.ndarray:
+    U = np.array(U, dtype=np.float64, order="C", copy=True)
+    assert U.ndim == 4 and U.shape[0] == 8 and U.shape[1] == U.shape[2] == U.shape[3]
+    return U
+
+
+def rhs(U, gamma=5.0 / 3.0, nu=0.0, eta=0.0) -> np.ndarray:
+    U = _fields(U)
+    R = np.empty_like(U)
+    p = _params(U.shape[1], gamma, nu, eta)
+    _check(lib().orc_rhs(ctypes.byref(p), _ptr(U), _ptr(R)), "rhs")
+    return R
+
+
+def run(U, nsteps: int, dt: float, gamma=5.0 / 3.0, nu=0.0, eta=0.0) -> np.ndarray:
+    U = _fields(U)
+    p = _params(U.shape[1], gamma, nu, eta, dt)
+    _check(lib().orc_run(ctypes.byref(p), _ptr(U), int(nsteps)), "run")
+    return U
+
+
+def diag(U, gamma=5.0 / 3.0, nu=0.0, eta=0.0, cfl=0.1) -> dict:
+    U = _fields(U)
+    out = np.zeros(len(DIAG_NAMES), dtype=np.float64)
+    p = _params(U.shape[1], gamma, nu, eta, 0.0, cfl)
+    _check(lib().orc_diag(ctypes.byref(p), _ptr(U), _ptr(out)), "diag")
+    return dict(zip(DIAG_NAMES, out.tolist()))
+
+
+def neumaier_sum(x) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return lib().orc_neumaier_sum(_ptr(x), x.size)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
