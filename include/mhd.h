@@ -1,0 +1,168 @@
+/*
+ * libmhd: MI355X (gfx950) pseudo-spectral compressible-MHD hot path.
+ *
+ * The library evolves the eight conserved fields of the paper's compressible
+ * MHD system (Section III, Eqs. MHD1-MHD4: mass, momentum, total energy,
+ * induction), in the normalised Heaviside-Lorentz units of Section V
+ * (magnetic pressure |B|^2/2, Lorentz stress B B), on the periodic box
+ * [0, 2*pi)^3 with an n^3 grid.  Spatial derivatives are pseudo-spectral
+ * (Section II: transform, multiply by i k, transform back; nonlinear products
+ * in real space), dealiased by the cubic 2/3 rule, and time advances with the
+ * second-order Adams-Bashforth scheme (Sections II and IV) started by one
+ * Euler step.  The closure is the ideal gas P = (gamma-1)(E - m.u/2 - |B|^2/2)
+ * with the energy equation MHD3.
+ *
+ * Conventions shared by every entry point
+ *  - Real field sets are device arrays [8][n][n][n], x fastest, field order
+ *    rho, m_x, m_y, m_z, B_x, B_y, B_z, E; element type given by `dtype`
+ *    (MHD_FP64 = double, MHD_FP32 = float).
+ *  - Forward DFT f^(k) = sum_x f(x) exp(-i k.x) (unnormalised); inverse with
+ *    1/n^3.  Wavenumber of index i is i for 2i < n, else i - n.
+ *  - A mode is retained iff 3|k| < n on all three axes; K = (n-1)/3 is the
+ *    largest retained |k| per axis.
+ *  - Compact spectra (the state and the mhd_fft3d hook) are complex arrays
+ *    [kz][ky][kx] of (2K+1) x (2K+1) x (K+1) interleaved (re, im) pairs in the
+ *    working precision; kz and ky run 0..K then -K..-1, kx runs 0..K.
+ *  - Every call enqueues work on the stream given to mhd_init and returns
+ *    without waiting, except where a function says it synchronises.
+ *  - All device memory belongs to the caller: the workspace passed to
+ *    mhd_init and the field arrays of each call.  The library never calls
+ *    hipMalloc or hipFree.  A context keeps pointers into its workspace, so
+ *    the workspace must outlive it.
+ *  - Functions return MHD_OK (0) or a negative MHD_E_* status; nothing throws
+ *    or exits.  After MHD_E_HIP, mhd_last_error gives the HIP error text.
+ *  - One context per stream; a context is not thread-safe.
+ *
+ * Supported sizes: n in {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384,
+ * 512} for MHD_FP64 and additionally 768 and 1024 for MHD_FP32
+ * (mhd_supported_size).
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MHD_OK = 0,
+    MHD_E_ARG = -1,       /* null pointer, bad enum, non-positive dt, ... */
+    MHD_E_SIZE = -2,      /* n not supported for this precision */
+    MHD_E_WORKSPACE = -3, /* workspace null, misaligned (256 B) or too small */
+    MHD_E_HIP = -4,       /* a HIP runtime call failed (see mhd_last_error) */
+    MHD_E_NONFINITE = -5, /* a non-finite value was found in the state */
+    MHD_E_CFL = -6,       /* dt exceeded the CFL limit (only with MHD_FLAG_CHECK_CFL) */
+    MHD_E_STATE = -7      /* no state has been set yet */
+};
+
+/* Working precision (mhd_params.precision) and real-field element types. */
+enum { MHD_FP64 = 0, MHD_FP32 = 1 };
+
+/* mhd_params.flags */
+enum {
+    MHD_FLAG_CHECK_CFL = 1 /* mhd_diagnostics reports MHD_E_CFL when dt > dt_cfl seen by a step */
+};
+
+typedef struct {
+    int32_t n;         /* grid points per side */
+    int32_t precision; /* MHD_FP64 or MHD_FP32 */
+    int32_t flags;     /* MHD_FLAG_* */
+    int32_t reserved;  /* must be 0 */
+    double gamma;      /* ratio of specific heats, > 1 */
+    double nu;         /* kinematic viscosity, >= 0 (Eq. MHD2: div(2 nu rho S)) */
+    double eta;        /* magnetic diffusivity, >= 0 (Eq. MHD4: eta lap B) */
+    double dt;         /* fixed time step, > 0 */
+    double cfl;        /* Courant number of the dt_cfl diagnostic, > 0 (e.g. 0.1) */
+} mhd_params;
+
+/* FP64 volume-mean diagnostics of the current state (Section III: dynamic
+ * sound speed c_s = sqrt(gamma <P>/<rho>), Alfven speed and Mach numbers;
+ * Section V: energies per grid point). */
+typedef struct {
+    double t;          /* simulated time */
+    int64_t step;      /* steps taken since mhd_set_state */
+    double mass;       /* <rho> */
+    double mom[3];     /* <m> */
+    double e_kin;      /* <m.u/2> */
+    double e_mag;      /* <|B|^2/2> */
+    double e_int;      /* <P>/(gamma-1) */
+    double e_tot;      /* <E> */
+    double h_cross;    /* <u.B> */
+    double h_mag;      /* <A.B>, Coulomb gauge, k = 0 excluded */
+    double divb_rms;   /* <(div B)^2>^(1/2) (Parseval) */
+    double divb_max;   /* max |div B| over the grid */
+    double divb_rel;   /* divb_rms / <|curl B|^2>^(1/2) */
+    double j_rms;      /* <|curl B|^2>^(1/2) */
+    double dt_cfl;     /* cfl * (2 pi/n) / max(max_i |u_i| + c_f), c_f^2 = (gamma P + |B|^2)/rho */
+    double c_s;        /* sqrt(gamma <P> / <rho>) */
+    double v_a;        /* <|B|> / sqrt(<rho>) */
+    double mach_s;     /* <|u|> / c_s */
+    double mach_a;     /* <|u|> / v_a */
+    int64_t nonfinite; /* non-finite values in the real-space state */
+} mhd_diag;
+
+typedef struct mhd_ctx mhd_ctx;
+
+/* 1 if n is supported for `precision`, else 0. */
+int mhd_supported_size(int32_t n, int32_t precision);
+
+/* Bytes of device workspace mhd_init needs for these parameters, or 0 if the
+ * parameters are invalid. */
+size_t mhd_workspace_bytes(const mhd_params* p);
+
+/* Creates a context.  d_workspace: caller-owned device memory of at least
+ * mhd_workspace_bytes(p) bytes, 256-byte aligned.  hip_stream: the hipStream_t
+ * every later call enqueues on (NULL = default stream).  Uploads the twiddle
+ * tables (synchronously).  *out receives the context. */
+int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream, mhd_ctx** out);
+
+/* Sets the state to D F[U] for the real fields U = d_fields ([8][n][n][n],
+ * element type dtype), resets t, the step count and the AB2 history (the next
+ * step is an Euler step).  Inputs are rounded to the working precision. */
+int mhd_set_state(mhd_ctx* ctx, const void* d_fields, int32_t dtype);
+
+/* Writes F^-1 of the state to d_fields ([8][n][n][n], element type dtype). */
+int mhd_get_state(mhd_ctx* ctx, void* d_fields, int32_t dtype);
+
+/* Pure right-hand side (Eqs. MHD1-MHD4): d_rhs_out = F^-1 R(D F[U]) for the
+ * real fields U = d_fields_in; the context's state and history are untouched.
+ * Both arrays [8][n][n][n] of element type dtype; they may not overlap. */
+int mhd_rhs(mhd_ctx* ctx, const void* d_fields_in, void* d_rhs_out, int32_t dtype);
+
+/* Advances the state by nsteps >= 0 AB2 steps of the fixed dt
+ * (U^{n+1} = U^n + dt (3/2 R^n - 1/2 R^{n-1}); the first step after
+ * mhd_set_state is Euler).  Returns MHD_E_STATE if no state is set. */
+int mhd_step(mhd_ctx* ctx, int32_t nsteps);
+
+/* Computes the diagnostics of the current state into *h_out (host memory)
+ * and synchronises the stream.  Returns MHD_E_NONFINITE if the state holds a
+ * non-finite value, MHD_E_CFL if MHD_FLAG_CHECK_CFL is set and some step since
+ * mhd_set_state ran with dt above its CFL limit; *h_out is filled either way. */
+int mhd_diagnostics(mhd_ctx* ctx, mhd_diag* h_out);
+
+/* Test hook with the transform conventions above.  dir = -1: d_in is one real
+ * n^3 field, d_out its compact spectrum D F[f].  dir = +1: d_in a compact
+ * spectrum, d_out the real field F^-1 (n^-3 normalised).  Both in the working
+ * precision; the arrays may not overlap.  Uses the context's workspace. */
+int mhd_fft3d(mhd_ctx* ctx, int32_t dir, const void* d_in, void* d_out);
+
+/* Number of complex values of one compact spectrum, (2K+1)^2 (K+1). */
+int64_t mhd_spectrum_size(int32_t n);
+
+/* Releases the host-side context (not the caller's workspace). */
+int mhd_destroy(mhd_ctx* ctx);
+
+/* Static text of a status code. */
+const char* mhd_status_string(int status);
+
+/* Text of the last HIP error seen by ctx ("" if none). */
+const char* mhd_last_error(const mhd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MHD_H */

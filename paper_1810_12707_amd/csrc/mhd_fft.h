@@ -1,0 +1,192 @@
+// Batched in-LDS FFTs for gfx950.
+//
+// A workgroup holds NB sequences of length N in LDS, element (b, l) at
+// buf[b*BS + l*ES].  Each radix-R pass of the Stockham autosort (decimation
+// in time) lets every thread read R elements of one butterfly into registers,
+// twiddle them, do an R-point DFT in registers, and, after a barrier, write
+// them to their sorted positions; the output ends in natural order, so no
+// bit-reversal pass is needed.  Butterflies are assigned batch-fastest across
+// lanes so that a column tile (ES = C, BS = 1) gives unit-stride LDS access.
+//
+// Twiddles come from a table of exp(-2 pi i j / N), j < N, computed in FP64
+// on the host and rounded once to T; the inverse uses the conjugates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mhd {
+
+template <typename T> struct V2;
+template <> struct V2<float> { using t = float2; };
+template <> struct V2<double> { using t = double2; };
+template <typename T> using cx = typename V2<T>::t;
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename X> __device__ __forceinline__ X cadd(X a, X b) { X r; r.x = a.x + b.x; r.y = a.y + b.y; return r; }
+template <typename X> __device__ __forceinline__ X csub(X a, X b) { X r; r.x = a.x - b.x; r.y = a.y - b.y; return r; }
+template <typename X> __device__ __forceinline__ X cmul(X a, X b) {
+  X r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+// a * conj(b)
+template <typename X> __device__ __forceinline__ X cmulc(X a, X b) {
+  X r; r.x = a.x * b.x + a.y * b.y; r.y = a.y * b.x - a.x * b.y; return r;
+}
+template <typename X> __device__ __forceinline__ X cconj(X a) { X r; r.x = a.x; r.y = -a.y; return r; }
+template <typename X, typename S> __device__ __forceinline__ X cscale(X a, S s) { X r; r.x = a.x * s; r.y = a.y * s; return r; }
+// i * a and -i * a
+template <typename X> __device__ __forceinline__ X ctimes_i(X a) { X r; r.x = -a.y; r.y = a.x; return r; }
+template <typename X> __device__ __forceinline__ X ctimes_mi(X a) { X r; r.x = a.y; r.y = -a.x; return r; }
+// multiply by i^s: sign s = -1 gives -i (forward), +1 gives +i (inverse)
+template <int S, typename X> __device__ __forceinline__ X ctimes_si(X a) { return S < 0 ? ctimes_mi(a) : ctimes_i(a); }
+
+// ---------------------------------------------------------------- small DFTs
+// In place, natural order in and out; S = -1 forward, +1 inverse.
+
+template <int S, typename X> __device__ __forceinline__ void dft2(X* v) {
+  X t = csub(v[0], v[1]);
+  v[0] = cadd(v[0], v[1]);
+  v[1] = t;
+}
+
+template <int S, typename X> __device__ __forceinline__ void dft3(X* v) {
+  using T = decltype(v[0].x);
+  const T h = T(0.86602540378443864676372317075294);  // sin(pi/3)
+  X t = cadd(v[1], v[2]);
+  X d = csub(v[1], v[2]);
+  X m = csub(v[0], cscale(t, T(0.5)));
+  v[0] = cadd(v[0], t);
+  X sd = ctimes_si<S>(cscale(d, h));  // S * i * sin(pi/3) * (v1 - v2)
+  v[1] = cadd(m, sd);
+  v[2] = csub(m, sd);
+}
+
+template <int S, typename X> __device__ __forceinline__ void dft4(X* v) {
+  X t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  X t2 = cadd(v[1], v[3]), t3 = ctimes_si<S>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <int S, typename X> __device__ __forceinline__ void dft8(X* v) {
+  using T = decltype(v[0].x);
+  const T h = T(0.70710678118654752440084436210485);
+  X e[4] = {v[0], v[2], v[4], v[6]};
+  X o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<S>(e);
+  dft4<S>(o);
+  // o[q] *= exp(S * i * pi * q / 4)
+  X o1 = o[1], o3 = o[3];
+  if (S < 0) {
+    o[1].x = (o1.x + o1.y) * h; o[1].y = (o1.y - o1.x) * h;
+    o[3].x = (o3.y - o3.x) * h; o[3].y = -(o3.x + o3.y) * h;
+  } else {
+    o[1].x = (o1.x - o1.y) * h; o[1].y = (o1.x + o1.y) * h;
+    o[3].x = -(o3.x + o3.y) * h; o[3].y = (o3.x - o3.y) * h;
+  }
+  o[2] = ctimes_si<S>(o[2]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = cadd(e[q], o[q]);
+    v[q + 4] = csub(e[q], o[q]);
+  }
+}
+
+template <int R, int S, typename X> __device__ __forceinline__ void dft(X* v) {
+  if constexpr (R == 2) dft2<S>(v);
+  else if constexpr (R == 3) dft3<S>(v);
+  else if constexpr (R == 4) dft4<S>(v);
+  else if constexpr (R == 8) dft8<S>(v);
+  else static_assert(R == 2 || R == 3 || R == 4 || R == 8, "unsupported radix");
+}
+
+// ---------------------------------------------------------------- radix plans
+
+template <int N> struct Plan;
+#define MHD_PLAN(NN, ...)                                              \
+  template <> struct Plan<NN> {                                        \
+    static constexpr int r[] = {__VA_ARGS__};                          \
+    static constexpr int np = sizeof(r) / sizeof(int);                 \
+  };
+MHD_PLAN(8, 8)
+MHD_PLAN(12, 4, 3)
+MHD_PLAN(16, 4, 4)
+MHD_PLAN(24, 8, 3)
+MHD_PLAN(32, 8, 4)
+MHD_PLAN(48, 4, 4, 3)
+MHD_PLAN(64, 8, 8)
+MHD_PLAN(96, 8, 4, 3)
+MHD_PLAN(128, 8, 4, 4)
+MHD_PLAN(192, 8, 8, 3)
+MHD_PLAN(256, 8, 8, 4)
+MHD_PLAN(384, 8, 4, 4, 3)
+MHD_PLAN(512, 8, 8, 8)
+MHD_PLAN(768, 8, 8, 4, 3)
+MHD_PLAN(1024, 8, 8, 4, 4)
+#undef MHD_PLAN
+
+template <int N> constexpr int plan_ns(int p) {
+  int ns = 1;
+  for (int i = 0; i < p; ++i) ns *= Plan<N>::r[i];
+  return ns;
+}
+
+template <int N> constexpr bool plan_ok() {
+  int prod = 1;
+  for (int i = 0; i < Plan<N>::np; ++i) prod *= Plan<N>::r[i];
+  return prod == N;
+}
+
+// One Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P>
+__device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
+  constexpr int R = Plan<N>::r[P];
+  constexpr int NS = plan_ns<N>(P);
+  constexpr int NBF = N / R;
+  constexpr int TOT = NB * NBF;
+  constexpr int CNT = (TOT + NT - 1) / NT;
+  cx<T> v[CNT][R];
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
+    const int w = tid + i * NT;
+    const int b = w % NB, j = w / NB;
+    if ((TOT % NT == 0 || w < TOT) && b < b_act) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[b * BS + (j + r * NBF) * ES];
+      if constexpr (NS > 1) {
+        const int k = j % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cx<T> t = tw[k * r * (N / (NS * R))];
+          v[i][r] = (S < 0) ? cmul(v[i][r], t) : cmulc(v[i][r], t);
+        }
+      }
+      dft<R, S>(v[i]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
+    const int w = tid + i * NT;
+    const int b = w % NB, j = w / NB;
+    if ((TOT % NT == 0 || w < TOT) && b < b_act) {
+      const int k = j % NS;
+      const int d = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[b * BS + (d + r * NS) * ES] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P = 0>
+__device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
+  static_assert(plan_ok<N>(), "radix plan does not multiply to N");
+  if constexpr (P < Plan<N>::np) {
+    fft_pass<T, N, NB, NT, ES, BS, S, P>(buf, tw, tid, b_act);
+    lds_fft<T, N, NB, NT, ES, BS, S, P + 1>(buf, tw, tid, b_act);
+  }
+}
+
+}  // namespace mhd

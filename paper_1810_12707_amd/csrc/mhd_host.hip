@@ -1,0 +1,749 @@
+// libmhd host side: the C-ABI of include/mhd.h, workspace carving, twiddle
+// tables, the pass pipelines of the right-hand side and the FP64 reductions.
+//
+// One right-hand-side evaluation (Eqs. MHD1-MHD4) runs as two phases:
+//   A: rho^, m^ --inverse z, y--> x-pass (u = m/rho, forward x) --forward y, z--> u^ = D F[u]
+//   B: B^, E^, u^ --inverse z with the spectral multipliers for S and J = curl B--> inverse y
+//      --> x-pass (all fluxes at every grid point) --> forward y
+//      --> forward z with divergence / curl, resistive term and the AB2 update.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <string>
+
+#include "../../include/mhd.h"
+#include "mhd_internal.h"
+#include "mhd_registry.h"
+
+namespace mhd {
+
+Registry& registry() {
+  static Registry* r = [] {
+    Registry* reg = new Registry();
+#define MHD_CALL_REGISTER(NN) register_##NN(*reg);
+    MHD_SIZES(MHD_CALL_REGISTER)
+#undef MHD_CALL_REGISTER
+    return reg;
+  }();
+  return *r;
+}
+
+// ------------------------------------------------------------------ reductions
+
+// Block q reduces column q of part[nrec][nq]: thread t takes records t, t+256,
+// ... with a Neumaier sum (or a NaN-propagating max when bit q of max_mask is
+// set); thread 0 then combines the 256 partials in thread order.  The result
+// is written to out[q], or merged as max(out[q], result) when merge_max.
+__global__ void __launch_bounds__(kThreads)
+k_reduce(const double* __restrict__ part, int64_t nrec, int nq, unsigned max_mask, int merge_max,
+         double* __restrict__ out) {
+  __shared__ double s_s[kThreads];
+  __shared__ double s_c[kThreads];
+  const int q = blockIdx.x;
+  const int tid = threadIdx.x;
+  const bool is_max = (max_mask >> q) & 1u;
+  double s = 0.0, c = 0.0;
+  for (int64_t r = tid; r < nrec; r += kThreads) {
+    const double x = part[r * nq + q];
+    if (is_max) {
+      if (!(x <= s)) s = x;
+    } else {
+      const double t = s + x;
+      if (fabs(s) >= fabs(x)) c += (s - t) + x;
+      else c += (x - t) + s;
+      s = t;
+    }
+  }
+  s_s[tid] = s;
+  s_c[tid] = c;
+  __syncthreads();
+  if (tid == 0) {
+    double S = 0.0, Cc = 0.0;
+    for (int i = 0; i < kThreads; ++i) {
+      if (is_max) {
+        if (!(s_s[i] <= S)) S = s_s[i];
+      } else {
+        const double x = s_s[i];
+        const double t = S + x;
+        if (fabs(S) >= fabs(x)) Cc += (S - t) + x;
+        else Cc += (x - t) + S;
+        S = t;
+        Cc += s_c[i];
+      }
+    }
+    const double r = is_max ? S : S + Cc;
+    if (merge_max) {
+      if (!(r <= out[q])) out[q] = r;
+    } else {
+      out[q] = r;
+    }
+  }
+}
+
+// Spectral sums over the compact B^ (half spectrum: kx > 0 modes count twice):
+// sum Re(J^ . conj B^)/|k|^2, sum |i k.B^|^2, sum |J^|^2 with J^ = i k x B^.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz, Geo g,
+            double* __restrict__ part) {
+  __shared__ double s[kThreads];
+  const int tid = threadIdx.x;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + tid;
+  double q[kSpecQ] = {0.0, 0.0, 0.0};
+  if (idx < g.sc) {
+    const int64_t plane = (int64_t)g.nb * g.nh;
+    const int lz = (int)(idx / plane);
+    const int rem = (int)(idx - (int64_t)lz * plane);
+    const int ly = rem / g.nh, kx = rem - ly * g.nh;
+    const int kz = lz <= g.K ? lz : lz - g.nb;
+    const int ky = ly <= g.K ? ly : ly - g.nb;
+    const double w = kx == 0 ? 1.0 : 2.0;
+    const double Xr = bx[2 * idx], Xi = bx[2 * idx + 1];
+    const double Yr = by[2 * idx], Yi = by[2 * idx + 1];
+    const double Zr = bz[2 * idx], Zi = bz[2 * idx + 1];
+    // c = k x B (real cross product of k with re and im parts); J^ = i c
+    const double cxr = ky * Zr - kz * Yr, cxi = ky * Zi - kz * Yi;
+    const double cyr = kz * Xr - kx * Zr, cyi = kz * Xi - kx * Zi;
+    const double czr = kx * Yr - ky * Xr, czi = kx * Yi - ky * Xi;
+    const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+    // Re(i c . conj B) = -(Im c . Re B) + (Re c . Im B)
+    const double jb = -(cxi * Xr + cyi * Yr + czi * Zr) + (cxr * Xi + cyr * Yi + czr * Zi);
+    q[SQ_HM] = k2 > 0 ? w * jb / k2 : 0.0;
+    const double dr = kx * Xr + ky * Yr + kz * Zr, di = kx * Xi + ky * Yi + kz * Zi;
+    q[SQ_DIVB2] = w * (dr * dr + di * di);
+    q[SQ_J2] = w * (cxr * cxr + cxi * cxi + cyr * cyr + cyi * cyi + czr * czr + czi * czi);
+  }
+  for (int i = 0; i < kSpecQ; ++i) {
+    __syncthreads();
+    s[tid] = q[i];
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if (tid < w) s[tid] += s[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) part[(int64_t)blockIdx.x * kSpecQ + i] = s[0];
+  }
+}
+
+__global__ void k_fill(double* p, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace mhd
+
+using namespace mhd;
+
+// ------------------------------------------------------------------ context
+
+namespace {
+
+constexpr int kStatusWords = 4;  // [0] max CFL speed seen by steps, [1] non-finite seen
+constexpr int kResWords = 32;    // reduced diagnostics
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool size_ok(int32_t n, int32_t prec) {
+  if (n < 8 || n > 1024) return false;
+  bool listed = false;
+#define MHD_LISTED(NN) listed = listed || (n == NN);
+  MHD_SIZES(MHD_LISTED)
+#undef MHD_LISTED
+  if (!listed) return false;
+  if (prec == MHD_FP64 && n > 512) return false;
+  return prec == MHD_FP64 || prec == MHD_FP32;
+}
+
+Geo make_geo(int n) {
+  Geo g;
+  g.n = n;
+  g.K = (n - 1) / 3;
+  g.nh = g.K + 1;
+  g.nb = 2 * g.K + 1;
+  g.sc = (int64_t)g.nb * g.nb * g.nh;
+  g.iz = (int64_t)n * g.nb * g.nh;
+  g.iy = (int64_t)n * n * g.nh;
+  g.n3 = (int64_t)n * n * n;
+  return g;
+}
+
+struct Layout {
+  size_t tw, state, rprev, uhat, tstate, trhs, iz, iy, part, status, res, total;
+};
+
+Layout make_layout(const Geo& g, size_t tsize) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  const size_t cplx = 2 * tsize;
+  L.tw = take((size_t)g.n * cplx);
+  L.state = take(8 * (size_t)g.sc * cplx);
+  L.rprev = take(8 * (size_t)g.sc * cplx);
+  L.uhat = take(3 * (size_t)g.sc * cplx);
+  L.tstate = take(8 * (size_t)g.sc * cplx);
+  L.trhs = take(8 * (size_t)g.sc * cplx);
+  L.iz = take(12 * (size_t)g.iz * cplx);
+  L.iy = take(16 * (size_t)g.iy * cplx);
+  const size_t rows = (size_t)g.n * g.n / 2;
+  const size_t spec_blocks = (size_t)((g.sc + kThreads - 1) / kThreads);
+  size_t pd = rows * kDiagQ;
+  if (spec_blocks * kSpecQ > pd) pd = spec_blocks * kSpecQ;
+  L.part = take(pd * sizeof(double));
+  L.status = take(kStatusWords * sizeof(double));
+  L.res = take(kResWords * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct mhd_ctx {
+  mhd_params p;
+  Geo g;
+  Layout L;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  bool has_state;
+  bool first_step;
+  int64_t step;
+  double t;
+  std::string last_err;
+};
+
+namespace {
+
+int hip_fail(mhd_ctx* c, hipError_t e, const char* what) {
+  if (c) {
+    c->last_err = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return MHD_E_HIP;
+}
+
+int check_launch(mhd_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return MHD_OK;
+}
+
+Term term(int src, int axis, double coef) {
+  Term t;
+  t.src = src;
+  t.axis = axis;
+  t.coef = coef;
+  return t;
+}
+
+OutSpec spec(std::initializer_list<Term> ts) {
+  OutSpec s;
+  std::memset(&s, 0, sizeof(s));
+  s.nterms = 0;
+  for (const Term& t : ts) s.t[s.nterms++] = t;
+  return s;
+}
+
+OutSpec copy_spec(int src, double coef) { return spec({term(src, -1, coef)}); }
+
+template <typename T>
+struct Engine {
+  mhd_ctx* c;
+  const Kern<T>& k;
+  const Geo& g;
+
+  Engine(mhd_ctx* ctx, const Kern<T>& kern) : c(ctx), k(kern), g(ctx->g) {}
+
+  T* at(size_t off) const { return reinterpret_cast<T*>(c->ws + off); }
+  T* state() const { return at(c->L.state); }
+  T* rprev() const { return at(c->L.rprev); }
+  T* uhat() const { return at(c->L.uhat); }
+  T* tstate() const { return at(c->L.tstate); }
+  T* trhs() const { return at(c->L.trhs); }
+  T* tw() const { return at(c->L.tw); }
+  T* iz(int slot) const { return at(c->L.iz) + 2 * (size_t)slot * g.iz; }
+  T* iy(int slot) const { return at(c->L.iy) + 2 * (size_t)slot * g.iy; }
+  T* spec_field(T* base, int f) const { return base + 2 * (size_t)f * g.sc; }
+  double* part() const { return reinterpret_cast<double*>(c->ws + c->L.part); }
+  double* status() const { return reinterpret_cast<double*>(c->ws + c->L.status); }
+  double* res() const { return reinterpret_cast<double*>(c->ws + c->L.res); }
+
+  int ztiles() const { return (int)((g.nb * g.nh + k.col_width - 1) / k.col_width); }
+  int ytiles() const { return (g.nh + k.col_width - 1) / k.col_width; }
+
+  ColArgs<T> col_args(int kind, int nout) const {
+    ColArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.kind = kind;
+    a.nout = nout;
+    a.tw = tw();
+    a.g = g;
+    return a;
+  }
+
+  // Launch a column pass; ins/outs are per-launch slot lists.
+  void col(int kind, int nout, const T* const* ins, int nin, T* const* outs, const OutSpec* specs) {
+    ColArgs<T> a = col_args(kind, nout);
+    for (int i = 0; i < nin; ++i) a.in[i] = ins[i];
+    for (int f = 0; f < nout; ++f) {
+      a.out[f] = outs[f];
+      a.spec[f] = specs[f];
+    }
+    const bool z = (kind == PK_ZINV || kind == PK_ZFWD);
+    dim3 grid(z ? ztiles() : g.n * ytiles(), nout);
+    if (kind == PK_ZINV || kind == PK_YINV) k.col_inv(a, grid, c->stream);
+    else k.col_fwd(a, grid, c->stream);
+  }
+
+  // Copy-only y passes of `count` fields from slot lists.
+  void y_copy(int kind, int count, T* const* ins, T* const* outs) {
+    OutSpec sp[kMaxOut];
+    for (int f = 0; f < count; ++f) sp[f] = copy_spec(f, 1.0);
+    col(kind, count, ins, count, outs, sp);
+  }
+
+  RowArgs<T> row_args() const {
+    RowArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.gamma = c->p.gamma;
+    a.nu = c->p.nu;
+    a.eta = c->p.eta;
+    a.tw = tw();
+    a.g = g;
+    return a;
+  }
+
+  dim3 row_grid() const { return dim3((unsigned)((int64_t)g.n * g.n / 2)); }
+
+  double inv_n3() const { return 1.0 / (double)g.n3; }
+
+  // Real fields [nf][n^3] (dtype) -> compact spectra D F[f] at dst.
+  void forward_real(const void* real, int dtype, int nf, T* dst) {
+    RowArgs<T> r = row_args();
+    r.real_in = real;
+    r.real_dtype = dtype == MHD_FP64 ? 0 : 1;
+    r.nf = nf;
+    for (int f = 0; f < nf; ++f) r.out[f] = iy(f);
+    k.row(RM_XFWD_REAL, r, row_grid(), c->stream);
+    T* yi[kMaxOut];
+    T* yo[kMaxOut];
+    for (int f = 0; f < nf; ++f) { yi[f] = iy(f); yo[f] = iz(f); }
+    y_copy(PK_YFWD, nf, yi, yo);
+    T* zo[kMaxOut];
+    for (int f = 0; f < nf; ++f) zo[f] = spec_field(dst, f);
+    OutSpec sp[kMaxOut];
+    for (int f = 0; f < nf; ++f) sp[f] = copy_spec(f, 1.0);
+    col(PK_ZFWD, nf, yo, nf, zo, sp);
+  }
+
+  // Compact spectra at src (nf fields) -> real fields [nf][n^3] (dtype).
+  void inverse_real(const T* src, int nf, void* real, int dtype) {
+    const T* zi[kMaxIn];
+    T* zo[kMaxOut];
+    OutSpec sp[kMaxOut];
+    for (int f = 0; f < nf; ++f) {
+      zi[f] = src + 2 * (size_t)f * g.sc;
+      zo[f] = iz(f);
+      sp[f] = copy_spec(f, inv_n3());
+    }
+    col(PK_ZINV, nf, zi, nf, zo, sp);
+    T* yo[kMaxOut];
+    for (int f = 0; f < nf; ++f) yo[f] = iy(f);
+    y_copy(PK_YINV, nf, zo, yo);
+    RowArgs<T> r = row_args();
+    r.real_out = real;
+    r.real_dtype = dtype == MHD_FP64 ? 0 : 1;
+    r.nf = nf;
+    for (int f = 0; f < nf; ++f) r.in[f] = iy(f);
+    k.row(RM_XINV_REAL, r, row_grid(), c->stream);
+  }
+
+  // Phase A: u^ = D F[m / rho] from the state U.
+  void phase_a(T* U) {
+    const T* zi[4];
+    T* zo[4];
+    OutSpec sp[4];
+    for (int f = 0; f < 4; ++f) {
+      zi[f] = spec_field(U, f);
+      zo[f] = iz(f);
+      sp[f] = copy_spec(f, inv_n3());
+    }
+    col(PK_ZINV, 4, zi, 4, zo, sp);
+    T* yo[4] = {iy(0), iy(1), iy(2), iy(3)};
+    y_copy(PK_YINV, 4, zo, yo);
+    RowArgs<T> r = row_args();
+    for (int f = 0; f < 4; ++f) r.in[f] = iy(f);
+    for (int f = 0; f < 3; ++f) r.out[f] = iy(4 + f);
+    k.row(RM_XA, r, row_grid(), c->stream);
+    T* ui[3] = {iy(4), iy(5), iy(6)};
+    T* uo[3] = {iz(0), iz(1), iz(2)};
+    y_copy(PK_YFWD, 3, ui, uo);
+    T* ho[3] = {spec_field(uhat(), 0), spec_field(uhat(), 1), spec_field(uhat(), 2)};
+    OutSpec cp[3] = {copy_spec(0, 1.0), copy_spec(1, 1.0), copy_spec(2, 1.0)};
+    col(PK_ZFWD, 3, uo, 3, ho, cp);
+  }
+
+  // Phase B: fluxes and the spectral RHS of state U.  rout == nullptr: AB2
+  // update of U and the history with coefficients (a_cur, a_prev).
+  void phase_b(T* U, T* rout, double a_cur, double a_prev) {
+    const double s = inv_n3();
+    // inputs: 0-2 B^, 3 E^, 4-6 u^
+    const T* zi[7] = {spec_field(U, 4), spec_field(U, 5), spec_field(U, 6), spec_field(U, 7),
+                      spec_field(uhat(), 0), spec_field(uhat(), 1), spec_field(uhat(), 2)};
+    enum { X = 0, Y = 1, Z = 2 };
+    const double t3 = s / 3.0, h = 0.5 * s;
+    OutSpec sp[12] = {
+        copy_spec(0, s), copy_spec(1, s), copy_spec(2, s), copy_spec(3, s),
+        // traceless strain (Eqs. 3-4): S_ij = (d_i u_j + d_j u_i)/2 - delta_ij div u / 3
+        spec({term(4, X, 2 * t3), term(5, Y, -t3), term(6, Z, -t3)}),  // S_xx
+        spec({term(4, X, -t3), term(5, Y, 2 * t3), term(6, Z, -t3)}),  // S_yy
+        spec({term(4, Y, h), term(5, X, h)}),                          // S_xy
+        spec({term(4, Z, h), term(6, X, h)}),                          // S_xz
+        spec({term(5, Z, h), term(6, Y, h)}),                          // S_yz
+        // J = curl B
+        spec({term(2, Y, s), term(1, Z, -s)}),  // J_x
+        spec({term(0, Z, s), term(2, X, -s)}),  // J_y
+        spec({term(1, X, s), term(0, Y, -s)}),  // J_z
+    };
+    T* zo[12];
+    for (int f = 0; f < 12; ++f) zo[f] = iz(f);
+    col(PK_ZINV, 12, zi, 7, zo, sp);
+    T* yo[12];
+    for (int f = 0; f < 12; ++f) yo[f] = iy(4 + f);
+    y_copy(PK_YINV, 12, zo, yo);
+    RowArgs<T> r = row_args();
+    for (int f = 0; f < 16; ++f) r.in[f] = iy(f);
+    for (int f = 0; f < 12; ++f) r.out[f] = iy(f);
+    r.partials = part();
+    k.row(RM_XB, r, row_grid(), c->stream);
+    if (!rout) {
+      // per-step CFL speed and non-finite count, merged into the status words
+      hipLaunchKernelGGL(k_reduce, dim3(2), dim3(kThreads), 0, c->stream, part(), (int64_t)g.n * g.n / 2, 2,
+                         1u | 2u, 1, status());
+    }
+    T* fi[12];
+    T* fo[12];
+    for (int f = 0; f < 12; ++f) { fi[f] = iy(f); fo[f] = iz(f); }
+    y_copy(PK_YFWD, 12, fi, fo);
+    RhsArgs<T> q;
+    std::memset(&q, 0, sizeof(q));
+    for (int f = 0; f < 12; ++f) q.flux[f] = iz(f);
+    // flux slots: 0 Pi_xx, 1 Pi_yy, 2 Pi_zz, 3 Pi_xy, 4 Pi_xz, 5 Pi_yz, 6-8 F^E, 9-11 e = u x B
+    // R_f = F_z[A_f] + i kz F_z[Z_f]
+    q.A[1] = spec({term(0, X, -1), term(3, Y, -1)});  // MHD2: -i k_j Pi_xj
+    q.Z[1] = spec({term(4, -1, -1)});
+    q.A[2] = spec({term(3, X, -1), term(1, Y, -1)});
+    q.Z[2] = spec({term(5, -1, -1)});
+    q.A[3] = spec({term(4, X, -1), term(5, Y, -1)});
+    q.Z[3] = spec({term(2, -1, -1)});
+    q.A[4] = spec({term(11, Y, 1)});                   // MHD4: i k x e
+    q.Z[4] = spec({term(10, -1, -1)});
+    q.A[5] = spec({term(11, X, -1)});
+    q.Z[5] = spec({term(9, -1, 1)});
+    q.A[6] = spec({term(10, X, 1), term(9, Y, -1)});
+    q.A[7] = spec({term(6, X, -1), term(7, Y, -1)});  // MHD3: -i k . F^E
+    q.Z[7] = spec({term(8, -1, -1)});
+    q.state = U;
+    q.rprev = rprev();
+    q.rout = rout;
+    q.tw = tw();
+    q.dt = c->p.dt;
+    q.a_cur = a_cur;
+    q.a_prev = a_prev;
+    q.eta = c->p.eta;
+    q.g = g;
+    k.rhs(q, dim3(ztiles(), 8), c->stream);
+  }
+
+  void reset_status() {
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kStatusWords), 0, c->stream, status(), kStatusWords, 0.0);
+  }
+
+  // Diagnostics pass over the state: real-space partials and spectral sums.
+  void diagnostics() {
+    const double s = inv_n3();
+    T* U = state();
+    const T* zi[8];
+    for (int f = 0; f < 8; ++f) zi[f] = spec_field(U, f);
+    enum { X = 0, Y = 1, Z = 2 };
+    OutSpec sp[12];
+    for (int f = 0; f < 8; ++f) sp[f] = copy_spec(f, s);
+    sp[8] = spec({term(6, Y, s), term(5, Z, -s)});   // J_x
+    sp[9] = spec({term(4, Z, s), term(6, X, -s)});   // J_y
+    sp[10] = spec({term(5, X, s), term(4, Y, -s)});  // J_z
+    sp[11] = spec({term(4, X, s), term(5, Y, s), term(6, Z, s)});  // div B
+    T* zo[12];
+    for (int f = 0; f < 12; ++f) zo[f] = iz(f);
+    col(PK_ZINV, 12, zi, 8, zo, sp);
+    T* yo[12];
+    for (int f = 0; f < 12; ++f) yo[f] = iy(f);
+    y_copy(PK_YINV, 12, zo, yo);
+    RowArgs<T> r = row_args();
+    for (int f = 0; f < 12; ++f) r.in[f] = iy(f);
+    r.partials = part();
+    k.row(RM_XDIAG, r, row_grid(), c->stream);
+    const unsigned maxmask = (1u << DQ_DIVB_MAX) | (1u << DQ_CFL_MAX);
+    hipLaunchKernelGGL(k_reduce, dim3(kDiagQ), dim3(kThreads), 0, c->stream, part(), (int64_t)g.n * g.n / 2,
+                       kDiagQ, maxmask, 0, res());
+    const int sblocks = (int)((g.sc + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_spec_diag<T>), dim3(sblocks), dim3(kThreads), 0, c->stream, spec_field(U, 4),
+                       spec_field(U, 5), spec_field(U, 6), g, part());
+    hipLaunchKernelGGL(k_reduce, dim3(kSpecQ), dim3(kThreads), 0, c->stream, part(), (int64_t)sblocks, kSpecQ, 0u,
+                       0, res() + 16);
+  }
+};
+
+const void* kern_for(const mhd_ctx* c) {
+  Registry& r = registry();
+  if (c->p.precision == MHD_FP32) return r.f32[c->p.n].row ? &r.f32[c->p.n] : nullptr;
+  return r.f64[c->p.n].row ? &r.f64[c->p.n] : nullptr;
+}
+
+template <typename F>
+int with_engine(mhd_ctx* c, F&& fn) {
+  const void* k = kern_for(c);
+  if (!k) return MHD_E_SIZE;
+  if (c->p.precision == MHD_FP32) {
+    Engine<float> e(c, *static_cast<const Kern<float>*>(k));
+    return fn(e);
+  }
+  Engine<double> e(c, *static_cast<const Kern<double>*>(k));
+  return fn(e);
+}
+
+int validate(const mhd_params* p) {
+  if (!p) return MHD_E_ARG;
+  if (p->precision != MHD_FP32 && p->precision != MHD_FP64) return MHD_E_ARG;
+  if (p->reserved != 0) return MHD_E_ARG;
+  if (!(p->gamma > 1.0) || !(p->nu >= 0.0) || !(p->eta >= 0.0) || !(p->dt > 0.0) || !(p->cfl > 0.0)) return MHD_E_ARG;
+  if (!std::isfinite(p->gamma) || !std::isfinite(p->nu) || !std::isfinite(p->eta) || !std::isfinite(p->dt) ||
+      !std::isfinite(p->cfl))
+    return MHD_E_ARG;
+  if (!size_ok(p->n, p->precision)) return MHD_E_SIZE;
+  return MHD_OK;
+}
+
+bool dtype_ok(int32_t d) { return d == MHD_FP32 || d == MHD_FP64; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ C-ABI
+
+extern "C" {
+
+int mhd_supported_size(int32_t n, int32_t precision) { return size_ok(n, precision) ? 1 : 0; }
+
+int64_t mhd_spectrum_size(int32_t n) {
+  if (n < 1) return 0;
+  return make_geo(n).sc;
+}
+
+size_t mhd_workspace_bytes(const mhd_params* p) {
+  if (validate(p) != MHD_OK) return 0;
+  const size_t ts = p->precision == MHD_FP32 ? sizeof(float) : sizeof(double);
+  return make_layout(make_geo(p->n), ts).total;
+}
+
+int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream, mhd_ctx** out) {
+  if (!out) return MHD_E_ARG;
+  *out = nullptr;
+  int v = validate(p);
+  if (v != MHD_OK) return v;
+  const size_t need = mhd_workspace_bytes(p);
+  if (!d_workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
+    return MHD_E_WORKSPACE;
+  mhd_ctx* c = new (std::nothrow) mhd_ctx();
+  if (!c) return MHD_E_ARG;
+  c->p = *p;
+  c->g = make_geo(p->n);
+  const size_t ts = p->precision == MHD_FP32 ? sizeof(float) : sizeof(double);
+  c->L = make_layout(c->g, ts);
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->ws = static_cast<char*>(d_workspace);
+  c->ws_bytes = ws_bytes;
+  c->has_state = false;
+  c->first_step = true;
+  c->step = 0;
+  c->t = 0.0;
+  if (!kern_for(c)) {
+    delete c;
+    return MHD_E_SIZE;
+  }
+  // twiddles exp(-2 pi i j / n) in FP64, rounded once to the working precision
+  const int n = p->n;
+  const double two_pi = 6.28318530717958647692528676655900577;
+  hipError_t e;
+  if (p->precision == MHD_FP32) {
+    float* h = new float[2 * (size_t)n];
+    for (int j = 0; j < n; ++j) {
+      h[2 * j] = (float)std::cos(two_pi * j / n);
+      h[2 * j + 1] = (float)-std::sin(two_pi * j / n);
+    }
+    e = hipMemcpyAsync(c->ws + c->L.tw, h, 2 * (size_t)n * sizeof(float), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    delete[] h;
+  } else {
+    double* h = new double[2 * (size_t)n];
+    for (int j = 0; j < n; ++j) {
+      h[2 * j] = std::cos(two_pi * j / n);
+      h[2 * j + 1] = -std::sin(two_pi * j / n);
+    }
+    e = hipMemcpyAsync(c->ws + c->L.tw, h, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    delete[] h;
+  }
+  if (e != hipSuccess) {
+    delete c;
+    return MHD_E_HIP;
+  }
+  *out = c;
+  return MHD_OK;
+}
+
+int mhd_set_state(mhd_ctx* c, const void* d_fields, int32_t dtype) {
+  if (!c || !d_fields || !dtype_ok(dtype)) return MHD_E_ARG;
+  int rc = with_engine(c, [&](auto& e) {
+    e.forward_real(d_fields, dtype, 8, e.state());
+    e.reset_status();
+    return check_launch(c, "mhd_set_state");
+  });
+  if (rc == MHD_OK) {
+    c->has_state = true;
+    c->first_step = true;
+    c->step = 0;
+    c->t = 0.0;
+  }
+  return rc;
+}
+
+int mhd_get_state(mhd_ctx* c, void* d_fields, int32_t dtype) {
+  if (!c || !d_fields || !dtype_ok(dtype)) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  return with_engine(c, [&](auto& e) {
+    e.inverse_real(e.state(), 8, d_fields, dtype);
+    return check_launch(c, "mhd_get_state");
+  });
+}
+
+int mhd_rhs(mhd_ctx* c, const void* d_in, void* d_out, int32_t dtype) {
+  if (!c || !d_in || !d_out || !dtype_ok(dtype)) return MHD_E_ARG;
+  return with_engine(c, [&](auto& e) {
+    e.forward_real(d_in, dtype, 8, e.tstate());
+    e.phase_a(e.tstate());
+    e.phase_b(e.tstate(), e.trhs(), 1.0, 0.0);
+    e.inverse_real(e.trhs(), 8, d_out, dtype);
+    return check_launch(c, "mhd_rhs");
+  });
+}
+
+int mhd_step(mhd_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  int rc = with_engine(c, [&](auto& e) {
+    for (int s = 0; s < nsteps; ++s) {
+      const bool first = c->first_step && s == 0;
+      e.phase_a(e.state());
+      e.phase_b(e.state(), nullptr, first ? 1.0 : 1.5, first ? 0.0 : -0.5);
+    }
+    return check_launch(c, "mhd_step");
+  });
+  if (rc == MHD_OK && nsteps > 0) {
+    c->first_step = false;
+    c->step += nsteps;
+    c->t += nsteps * c->p.dt;
+  }
+  return rc;
+}
+
+int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) {
+  if (!c || !h) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  int rc = with_engine(c, [&](auto& e) {
+    e.diagnostics();
+    return check_launch(c, "mhd_diagnostics");
+  });
+  if (rc != MHD_OK) return rc;
+  double res[kResWords];
+  double st[kStatusWords];
+  hipError_t err = hipMemcpyAsync(res, c->ws + c->L.res, sizeof(res), hipMemcpyDeviceToHost, c->stream);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(st, c->ws + c->L.status, sizeof(st), hipMemcpyDeviceToHost, c->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+  if (err != hipSuccess) return hip_fail(c, err, "mhd_diagnostics copy");
+  const Geo& g = c->g;
+  const double n3 = (double)g.n3;
+  const double inv6 = 1.0 / (n3 * n3);
+  const double gm1 = c->p.gamma - 1.0;
+  std::memset(h, 0, sizeof(*h));
+  h->t = c->t;
+  h->step = c->step;
+  h->mass = res[DQ_RHO] / n3;
+  h->mom[0] = res[DQ_MX] / n3;
+  h->mom[1] = res[DQ_MY] / n3;
+  h->mom[2] = res[DQ_MZ] / n3;
+  h->e_kin = res[DQ_EKIN] / n3;
+  h->e_mag = res[DQ_EMAG] / n3;
+  const double pmean = res[DQ_P] / n3;
+  h->e_int = pmean / gm1;
+  h->e_tot = res[DQ_E] / n3;
+  h->h_cross = res[DQ_HC] / n3;
+  h->h_mag = res[16 + SQ_HM] * inv6;
+  const double divb2 = res[16 + SQ_DIVB2] * inv6;
+  const double j2 = res[16 + SQ_J2] * inv6;
+  h->divb_rms = std::sqrt(divb2);
+  h->j_rms = std::sqrt(j2);
+  h->divb_rel = j2 > 0 ? std::sqrt(divb2 / j2) : 0.0;
+  h->divb_max = res[DQ_DIVB_MAX];
+  const double two_pi = 6.28318530717958647692528676655900577;
+  h->dt_cfl = c->p.cfl * (two_pi / g.n) / res[DQ_CFL_MAX];
+  h->c_s = std::sqrt(c->p.gamma * pmean / h->mass);
+  const double umean = res[DQ_UABS] / n3;
+  h->v_a = (res[DQ_BABS] / n3) / std::sqrt(h->mass);
+  h->mach_s = umean / h->c_s;
+  h->mach_a = h->v_a > 0 ? umean / h->v_a : INFINITY;
+  h->nonfinite = (int64_t)res[DQ_NONFINITE];
+  if (h->nonfinite > 0 || st[1] > 0 || !(st[0] == st[0])) return MHD_E_NONFINITE;
+  if ((c->p.flags & MHD_FLAG_CHECK_CFL) && st[0] > 0) {
+    const double dt_lim = c->p.cfl * (two_pi / g.n) / st[0];
+    if (c->p.dt > dt_lim) return MHD_E_CFL;
+  }
+  return MHD_OK;
+}
+
+int mhd_fft3d(mhd_ctx* c, int32_t dir, const void* d_in, void* d_out) {
+  if (!c || !d_in || !d_out || (dir != 1 && dir != -1)) return MHD_E_ARG;
+  return with_engine(c, [&](auto& e) {
+    using T = std::remove_pointer_t<decltype(e.state())>;
+    if (dir < 0) {
+      e.forward_real(d_in, c->p.precision, 1, static_cast<T*>(d_out));
+    } else {
+      e.inverse_real(static_cast<const T*>(d_in), 1, d_out, c->p.precision);
+    }
+    return check_launch(c, "mhd_fft3d");
+  });
+}
+
+int mhd_destroy(mhd_ctx* c) {
+  delete c;
+  return MHD_OK;
+}
+
+const char* mhd_status_string(int s) {
+  switch (s) {
+    case MHD_OK: return "ok";
+    case MHD_E_ARG: return "invalid argument";
+    case MHD_E_SIZE: return "unsupported grid size for this precision";
+    case MHD_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case MHD_E_HIP: return "HIP runtime error";
+    case MHD_E_NONFINITE: return "non-finite value in the state";
+    case MHD_E_CFL: return "time step above the CFL limit";
+    case MHD_E_STATE: return "no state set";
+    default: return "unknown status";
+  }
+}
+
+const char* mhd_last_error(const mhd_ctx* c) { return c ? c->last_err.c_str() : ""; }
+
+}  // extern "C"

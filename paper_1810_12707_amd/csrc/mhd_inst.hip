@@ -1,0 +1,60 @@
+// Instantiates every pass kernel for one grid size N = MHD_N, both precisions
+// (FP64 only up to N = 512, where the row pass's LDS footprint still fits).
+#include "mhd_kernels.h"
+#include "mhd_registry.h"
+
+#ifndef MHD_N
+#error "compile with -DMHD_N=<grid size>"
+#endif
+
+namespace mhd {
+namespace {
+
+template <typename T, int N>
+void col_inv(const ColArgs<T>& a, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL((k_col<T, N, 1>), g, dim3(kThreads), 0, s, a);
+}
+template <typename T, int N>
+void col_fwd(const ColArgs<T>& a, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL((k_col<T, N, -1>), g, dim3(kThreads), 0, s, a);
+}
+template <typename T, int N>
+void rhs(const RhsArgs<T>& a, dim3 g, hipStream_t s) {
+  hipLaunchKernelGGL((k_zfwd_rhs<T, N>), g, dim3(kThreads), 0, s, a);
+}
+template <typename T, int N>
+void row(int mode, const RowArgs<T>& a, dim3 g, hipStream_t s) {
+  switch (mode) {
+    case RM_XA: hipLaunchKernelGGL((k_row<T, N, RM_XA>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XB: hipLaunchKernelGGL((k_row<T, N, RM_XB>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XFWD_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XFWD_REAL>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XINV_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XINV_REAL>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XDIAG: hipLaunchKernelGGL((k_row<T, N, RM_XDIAG>), g, dim3(kThreads), 0, s, a); break;
+    default: break;
+  }
+}
+
+template <typename T, int N>
+Kern<T> make() {
+  Kern<T> k;
+  k.n = N;
+  k.col_width = col_width<T, N>();
+  k.col_inv = col_inv<T, N>;
+  k.col_fwd = col_fwd<T, N>;
+  k.rhs = rhs<T, N>;
+  k.row = row<T, N>;
+  return k;
+}
+
+}  // namespace
+
+#define MHD_CAT2(a, b) a##b
+#define MHD_CAT(a, b) MHD_CAT2(a, b)
+void MHD_CAT(register_, MHD_N)(Registry& r) {
+  r.f32[MHD_N] = make<float, MHD_N>();
+#if MHD_N <= 512
+  r.f64[MHD_N] = make<double, MHD_N>();
+#endif
+}
+
+}  // namespace mhd

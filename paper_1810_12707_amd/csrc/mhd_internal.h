@@ -1,0 +1,101 @@
+// Internal definitions shared by the HIP kernels and the host side of libmhd.
+//
+// Data layout in HBM (per field, working precision T, complex = interleaved
+// (re, im) pairs; K = (n-1)/3, nh = K+1, nb = 2K+1):
+//   compact spectrum S  [kz: nb][ky: nb][kx: nh]  (state, history, u^)
+//   z-pass intermediate [z: n][ky: nb][kx: nh]    ("I_z")
+//   y-pass intermediate [z: n][y: n][kx: nh]      ("I_y")
+// Band indices run 0..K then -K..-1; along a length-n axis, band index l sits
+// at position l (l <= K) or l + n - nb (l > K).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mhd {
+
+constexpr int kThreads = 256;  // threads per workgroup of every pass kernel
+constexpr int kMaxTerms = 3;   // terms of one spectral linear combination
+constexpr int kMaxOut = 12;    // outputs of one column launch
+constexpr int kMaxIn = 12;     // inputs of one column launch
+constexpr int kRowFields = 16; // fields held by one row (x) pass
+constexpr int kDiagQ = 15;     // diagnostic partial sums per block
+constexpr int kSpecQ = 3;      // spectral diagnostic partial sums per block
+
+// Index of each real-space diagnostic partial.
+enum DiagQ {
+  DQ_RHO = 0, DQ_MX, DQ_MY, DQ_MZ, DQ_EKIN, DQ_EMAG, DQ_P, DQ_E, DQ_HC,
+  DQ_UABS, DQ_BABS, DQ_DIVB_MAX, DQ_CFL_MAX, DQ_NONFINITE, DQ_J2
+};
+// Index of each spectral diagnostic partial.
+enum SpecQ { SQ_HM = 0, SQ_DIVB2, SQ_J2 };
+
+// One term of out = sum_t coef_t * (i k_{axis_t} or 1) * in[src_t].
+struct Term {
+  int32_t src;   // input slot
+  int32_t axis;  // -1: no derivative; 0: x; 1: y; 2: z
+  double coef;
+};
+
+struct OutSpec {
+  int32_t nterms;
+  int32_t pad;
+  Term t[kMaxTerms];
+};
+
+enum PassKind { PK_ZINV = 0, PK_YINV = 1, PK_YFWD = 2, PK_ZFWD = 3 };
+
+struct Geo {
+  int32_t n, K, nh, nb;
+  int64_t sc;  // complex values per compact spectrum
+  int64_t iz;  // complex values per I_z field
+  int64_t iy;  // complex values per I_y field
+  int64_t n3;  // real values per field
+};
+
+template <typename T>
+struct ColArgs {
+  const T* in[kMaxIn];  // complex arrays (interleaved) in the pass's input layout
+  T* out[kMaxOut];
+  OutSpec spec[kMaxOut];
+  const T* tw;          // n twiddles exp(-2 pi i j / n), interleaved
+  int32_t kind;         // PassKind
+  int32_t nout;
+  Geo g;
+};
+
+// Forward-z pass that forms the right-hand side (Eqs. MHD1-MHD4 in spectral
+// form) and applies the AB2 update.  Output f is
+//   R_f = F_z[A_f] + i kz F_z[Z_f] - eta |k|^2 B^_f (f = 4, 5, 6),
+// with A_f, Z_f combinations of the y-transformed fluxes; R_rho = -i k.m^.
+template <typename T>
+struct RhsArgs {
+  const T* flux[kMaxIn];  // I_z flux slots
+  OutSpec A[8];
+  OutSpec Z[8];
+  T* state;               // compact [8][sc]
+  T* rprev;               // compact [8][sc] (R^{n-1}, overwritten with R^n)
+  T* rout;                // if non-null: store R here, leave state/rprev untouched
+  const T* tw;
+  double dt, a_cur, a_prev, eta;
+  Geo g;
+};
+
+enum RowMode { RM_XA = 0, RM_XB = 1, RM_XFWD_REAL = 2, RM_XINV_REAL = 3, RM_XDIAG = 4 };
+
+template <typename T>
+struct RowArgs {
+  const T* in[kRowFields];  // I_y slot bases (complex)
+  T* out[kRowFields];
+  const void* real_in;      // [nf][n^3] real rows (RM_XFWD_REAL)
+  void* real_out;           // [nf][n^3] real rows (RM_XINV_REAL)
+  int32_t real_dtype;       // 0 = double, 1 = float
+  int32_t nf;               // fields of an I/O pass
+  double gamma, nu, eta;
+  double* partials;         // per-block records
+  const T* tw;
+  Geo g;
+};
+
+}  // namespace mhd

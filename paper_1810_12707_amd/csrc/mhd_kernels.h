@@ -1,0 +1,484 @@
+// Pass kernels of the pseudo-spectral MHD right-hand side, templated on the
+// working precision T and the grid size N.
+//
+// Column passes (k_col, k_zfwd_rhs) transform along z or y for a tile of C
+// adjacent columns (the contiguous kx or (ky, kx) index), so every global
+// access is a run of C consecutive complex values; the tile sits in LDS as
+// [N][C].  Row passes (k_row) own two adjacent x rows (z, y) and (z, y+1) of
+// every field they touch: the two real rows of one field are packed as one
+// complex sequence (row0 + i row1), so one length-N complex FFT does two real
+// transforms, and all fields of a row pair are resident in LDS at once for the
+// pointwise work.
+#pragma once
+
+#include "mhd_fft.h"
+#include "mhd_internal.h"
+
+namespace mhd {
+
+template <int N> struct Band {
+  static constexpr int K = (N - 1) / 3;
+  static constexpr int NH = K + 1;
+  static constexpr int NB = 2 * K + 1;
+};
+
+// Position of band index l on a length-N axis, and its wavenumber.
+template <int N> __device__ __forceinline__ int band_pos(int l) { return l <= Band<N>::K ? l : l + N - Band<N>::NB; }
+template <int N> __device__ __forceinline__ int band_k(int l) { return l <= Band<N>::K ? l : l - Band<N>::NB; }
+
+// Column tile width: keeps the LDS tile at <= 64 KiB.
+template <typename T, int N> constexpr int col_width() {
+  constexpr int bytes = N * 2 * (int)sizeof(T);
+  constexpr int c = 65536 / bytes;
+  return c >= 16 ? 16 : (c >= 8 ? 8 : 4);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> ld(const T* base, int64_t idx) {
+  return reinterpret_cast<const cx<T>*>(base)[idx];
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, int64_t idx, cx<T> v) {
+  reinterpret_cast<cx<T>*>(base)[idx] = v;
+}
+
+// sum_t coef_t * (i k_axis or 1) * in[src_t][idx]
+template <typename T>
+__device__ __forceinline__ cx<T> combine(const OutSpec& sp, const T* const* in, int64_t idx, int kx, int ky, int kz) {
+  cx<T> acc = mk<T>(0, 0);
+  for (int t = 0; t < sp.nterms; ++t) {
+    const Term& tm = sp.t[t];
+    cx<T> v = ld(in[tm.src], idx);
+    T c = T(tm.coef);
+    if (tm.axis < 0) {
+      acc.x += c * v.x;
+      acc.y += c * v.y;
+    } else {
+      const T k = T(tm.axis == 0 ? kx : (tm.axis == 1 ? ky : kz));
+      const T ck = c * k;  // (c * i k) * v
+      acc.x -= ck * v.y;
+      acc.y += ck * v.x;
+    }
+  }
+  return acc;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_twiddles(cx<T>* stw, const T* tw, int tid) {
+  for (int i = tid; i < N; i += kThreads) stw[i] = ld(tw, i);
+}
+
+// ------------------------------------------------------------------ k_col
+// S = +1: inverse pass, band (nb) in -> N out.  S = -1: forward, N in -> band out.
+// blockIdx.x = outer * ntiles + tile, blockIdx.y = output field.
+template <typename T, int N, int S>
+__global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
+  constexpr int C = col_width<T, N>();
+  constexpr int K = Band<N>::K, NH = Band<N>::NH, NBB = Band<N>::NB;
+  __shared__ cx<T> tile[N * C];
+  __shared__ cx<T> stw[N];
+  const int tid = threadIdx.x;
+  const int f = blockIdx.y;
+  const bool zpass = (a.kind == PK_ZINV || a.kind == PK_ZFWD);
+  const int ncols = zpass ? NBB * NH : NH;
+  const int ntiles = (ncols + C - 1) / C;
+  const int outer = blockIdx.x / ntiles;
+  const int c0 = (blockIdx.x - outer * ntiles) * C;
+  // strides (complex elements) of the input and output layouts
+  int64_t os_in, ls_in, os_out, ls_out;
+  switch (a.kind) {
+    case PK_ZINV: os_in = 0; ls_in = NBB * NH; os_out = 0; ls_out = NBB * NH; break;
+    case PK_YINV: os_in = (int64_t)NBB * NH; ls_in = NH; os_out = (int64_t)N * NH; ls_out = NH; break;
+    case PK_YFWD: os_in = (int64_t)N * NH; ls_in = NH; os_out = (int64_t)NBB * NH; ls_out = NH; break;
+    default: os_in = 0; ls_in = NBB * NH; os_out = 0; ls_out = NBB * NH; break;
+  }
+  load_twiddles<T, N>(stw, a.tw, tid);
+  const OutSpec& sp = a.spec[f];
+  constexpr int LIN = (S > 0) ? NBB : N;
+  for (int e = tid; e < LIN * C; e += kThreads) {
+    const int l = e / C, c = e - (e / C) * C;
+    const int col = c0 + c;
+    cx<T> v = mk<T>(0, 0);
+    if (col < ncols) {
+      int kx = 0, ky = 0, kz = 0;
+      if (zpass) {
+        ky = band_k<N>(col / NH);
+        kx = col - (col / NH) * NH;
+        if (S > 0) kz = band_k<N>(l);
+      } else {
+        kx = col;
+        if (S > 0) ky = band_k<N>(l);
+      }
+      v = combine<T>(sp, a.in, outer * os_in + l * ls_in + col, kx, ky, kz);
+    }
+    const int pos = (S > 0) ? band_pos<N>(l) : l;
+    tile[pos * C + c] = v;
+  }
+  if constexpr (S > 0) {
+    for (int e = tid; e < (N - NBB) * C; e += kThreads) tile[(K + 1) * C + e] = mk<T>(0, 0);
+  }
+  __syncthreads();
+  lds_fft<T, N, C, kThreads, C, 1, S>(tile, stw, tid, C);
+  constexpr int LOUT = (S > 0) ? N : NBB;
+  T* out = a.out[f];
+  for (int e = tid; e < LOUT * C; e += kThreads) {
+    const int l = e / C, c = e - (e / C) * C;
+    const int col = c0 + c;
+    if (col < ncols) {
+      const int pos = (S > 0) ? l : band_pos<N>(l);
+      st(out, outer * os_out + l * ls_out + col, tile[pos * C + c]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ k_zfwd_rhs
+// blockIdx.x = column tile of (ky, kx), blockIdx.y = output field f (0..7).
+template <typename T, int N>
+__global__ void __launch_bounds__(kThreads) k_zfwd_rhs(const RhsArgs<T> a) {
+  constexpr int C = col_width<T, N>();
+  constexpr int NH = Band<N>::NH, NBB = Band<N>::NB;
+  constexpr int NCOLS = NBB * NH;
+  constexpr int CNT = (NBB * C + kThreads - 1) / kThreads;
+  __shared__ cx<T> tile[N * C];
+  __shared__ cx<T> stw[N];
+  const int tid = threadIdx.x;
+  const int f = blockIdx.y;
+  const int c0 = blockIdx.x * C;
+  const int64_t sc = a.g.sc;
+  const int64_t LS = NCOLS;  // row stride of I_z (z) and of compact (kz)
+  cx<T> acc[CNT];
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) acc[i] = mk<T>(0, 0);
+
+  if (f == 0) {
+    // MHD1: R_rho = -i k . m^ (state fields 1..3, already band-limited)
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) {
+      const int e = tid + i * kThreads;
+      const int l = e / C, c = e - (e / C) * C, col = c0 + c;
+      if (l < NBB && col < NCOLS) {
+        const int kz = band_k<N>(l), ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+        const int64_t idx = (int64_t)l * LS + col;
+        const cx<T> mx = ld(a.state, 1 * sc + idx), my = ld(a.state, 2 * sc + idx), mz = ld(a.state, 3 * sc + idx);
+        const T dx = T(kx) * mx.x + T(ky) * my.x + T(kz) * mz.x;
+        const T dy = T(kx) * mx.y + T(ky) * my.y + T(kz) * mz.y;
+        acc[i] = mk<T>(dy, -dx);  // -i (dx + i dy)
+      }
+    }
+  } else {
+    load_twiddles<T, N>(stw, a.tw, tid);
+    for (int grp = 0; grp < 2; ++grp) {
+      const OutSpec& sp = grp == 0 ? a.A[f] : a.Z[f];
+      if (sp.nterms == 0) continue;  // uniform across the block
+      if (grp == 1) __syncthreads();  // the tile is about to be overwritten
+      for (int e = tid; e < N * C; e += kThreads) {
+        const int l = e / C, c = e - (e / C) * C, col = c0 + c;
+        cx<T> v = mk<T>(0, 0);
+        if (col < NCOLS) {
+          const int ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+          v = combine<T>(sp, a.flux, (int64_t)l * LS + col, kx, ky, 0);
+        }
+        tile[l * C + c] = v;
+      }
+      __syncthreads();
+      lds_fft<T, N, C, kThreads, C, 1, -1>(tile, stw, tid, C);
+#pragma unroll
+      for (int i = 0; i < CNT; ++i) {
+        const int e = tid + i * kThreads;
+        const int l = e / C, c = e - (e / C) * C;
+        if (l < NBB) {
+          const cx<T> v = tile[band_pos<N>(l) * C + c];
+          if (grp == 0) {
+            acc[i] = cadd(acc[i], v);
+          } else {  // + i kz * v
+            const T kz = T(band_k<N>(l));
+            acc[i].x -= kz * v.y;
+            acc[i].y += kz * v.x;
+          }
+        }
+      }
+    }
+    if (f >= 4 && f <= 6) {
+      // MHD4 resistive term: - eta |k|^2 B^
+      const T eta = T(a.eta);
+#pragma unroll
+      for (int i = 0; i < CNT; ++i) {
+        const int e = tid + i * kThreads;
+        const int l = e / C, c = e - (e / C) * C, col = c0 + c;
+        if (l < NBB && col < NCOLS) {
+          const int kz = band_k<N>(l), ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+          const T k2 = T(kx * kx + ky * ky + kz * kz);
+          const cx<T> b = ld(a.state, f * sc + (int64_t)l * LS + col);
+          acc[i].x -= eta * k2 * b.x;
+          acc[i].y -= eta * k2 * b.y;
+        }
+      }
+    }
+  }
+  // store R, or the AB2 update U += dt (a_cur R^n + a_prev R^{n-1}); R^{n-1} <- R^n
+  const T dt = T(a.dt), ac = T(a.a_cur), ap = T(a.a_prev);
+  const bool use_prev = a.a_prev != 0.0;
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
+    const int e = tid + i * kThreads;
+    const int l = e / C, c = e - (e / C) * C, col = c0 + c;
+    if (l < NBB && col < NCOLS) {
+      const int64_t idx = f * sc + (int64_t)l * LS + col;
+      if (a.rout) {
+        st(a.rout, idx, acc[i]);
+      } else {
+        cx<T> u = ld(a.state, idx);
+        cx<T> inc = cscale(acc[i], ac);
+        if (use_prev) inc = cadd(inc, cscale(ld(a.rprev, idx), ap));
+        u.x += dt * inc.x;
+        u.y += dt * inc.y;
+        st(a.state, idx, u);
+        st(a.rprev, idx, acc[i]);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ k_row
+// blockIdx.x = row pair p: rows (z, 2y') and (z, 2y'+1), z = p / (N/2).
+template <int MODE> struct RowShape;
+template <> struct RowShape<RM_XA> { static constexpr int NIN = 4, NOUT = 3, NB = 4; };
+template <> struct RowShape<RM_XB> { static constexpr int NIN = 16, NOUT = 12, NB = 16; };
+template <> struct RowShape<RM_XFWD_REAL> { static constexpr int NIN = 8, NOUT = 8, NB = 8; };
+template <> struct RowShape<RM_XINV_REAL> { static constexpr int NIN = 8, NOUT = 8, NB = 8; };
+template <> struct RowShape<RM_XDIAG> { static constexpr int NIN = 12, NOUT = 0, NB = 12; };
+
+template <typename T>
+__device__ __forceinline__ bool finite_(T v) { return isfinite(v); }
+
+// Fixed-order tree reduction over the block (sum, or NaN-propagating max);
+// the result is valid in thread 0.  Deterministic for a given launch shape.
+__device__ __forceinline__ double block_reduce(double v, bool is_max, double* s, int tid) {
+  __syncthreads();
+  s[tid] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      const double o = s[tid + w];
+      if (is_max) {
+        if (!(o <= s[tid])) s[tid] = o;
+      } else {
+        s[tid] += o;
+      }
+    }
+    __syncthreads();
+  }
+  return s[0];
+}
+
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
+  constexpr int K = Band<N>::K, NH = Band<N>::NH;
+  constexpr int NB = RowShape<MODE>::NB;
+  constexpr int BS = N + 1;  // padded row pitch in LDS
+  __shared__ cx<T> buf[NB * BS];
+  __shared__ cx<T> stw[N];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x;
+  const int64_t row0 = 2 * (int64_t)p;  // flattened row index z*N + y of the first row
+  const int nin = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NIN;
+  const int nout = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NOUT;
+  load_twiddles<T, N>(stw, a.tw, tid);
+
+  if constexpr (MODE == RM_XFWD_REAL) {
+    // real rows -> packed complex row0 + i row1
+    for (int e = tid; e < nin * N; e += kThreads) {
+      const int fld = e / N, x = e - (e / N) * N;
+      const int64_t base = fld * a.g.n3 + row0 * N + x;
+      T r0, r1;
+      if (a.real_dtype == 0) {
+        r0 = T(static_cast<const double*>(a.real_in)[base]);
+        r1 = T(static_cast<const double*>(a.real_in)[base + N]);
+      } else {
+        r0 = T(static_cast<const float*>(a.real_in)[base]);
+        r1 = T(static_cast<const float*>(a.real_in)[base + N]);
+      }
+      buf[fld * BS + x] = mk<T>(r0, r1);
+    }
+    __syncthreads();
+  } else {
+    // Hermitian half rows (kx = 0..K) of two rows -> packed full spectrum
+    // Z[k] = X0[k] + i X1[k], Z[N-k] = conj(X0[k]) + i conj(X1[k]).
+    for (int e = tid; e < nin * N; e += kThreads) {
+      const int fld = e / N, q = e - (e / N) * N;
+      cx<T> z = mk<T>(0, 0);
+      if (q <= K || q >= N - K) {
+        const int k = q <= K ? q : N - q;
+        const cx<T> x0 = ld(a.in[fld], row0 * NH + k);
+        const cx<T> x1 = ld(a.in[fld], (row0 + 1) * NH + k);
+        if (q == 0) z = mk<T>(x0.x, x1.x);
+        else if (q <= K) z = mk<T>(x0.x - x1.y, x0.y + x1.x);
+        else z = mk<T>(x0.x + x1.y, x1.x - x0.y);
+      }
+      buf[fld * BS + q] = z;
+    }
+    __syncthreads();
+    lds_fft<T, N, NB, kThreads, 1, BS, +1>(buf, stw, tid, nin);
+  }
+
+  if constexpr (MODE == RM_XINV_REAL) {
+    for (int e = tid; e < nout * N; e += kThreads) {
+      const int fld = e / N, x = e - (e / N) * N;
+      const cx<T> z = buf[fld * BS + x];
+      const int64_t base = fld * a.g.n3 + row0 * N + x;
+      if (a.real_dtype == 0) {
+        static_cast<double*>(a.real_out)[base] = double(z.x);
+        static_cast<double*>(a.real_out)[base + N] = double(z.y);
+      } else {
+        static_cast<float*>(a.real_out)[base] = float(z.x);
+        static_cast<float*>(a.real_out)[base + N] = float(z.y);
+      }
+    }
+    return;
+  }
+
+  if constexpr (MODE == RM_XA) {
+    // u = m / rho, both rows at once
+    for (int x = tid; x < N; x += kThreads) {
+      const cx<T> rho = buf[0 * BS + x];
+      const T i0 = T(1) / rho.x, i1 = T(1) / rho.y;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const cx<T> m = buf[(1 + i) * BS + x];
+        buf[i * BS + x] = mk<T>(m.x * i0, m.y * i1);
+      }
+    }
+    __syncthreads();
+  }
+
+  if constexpr (MODE == RM_XB) {
+    // Real-space fluxes of Eqs. MHD2-MHD4 at every point of both rows.
+    // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8 S_xx, 9 S_yy, 10 S_xy, 11 S_xz,
+    // 12 S_yz, 13-15 J.  Outputs: 0 Pi_xx, 1 Pi_yy, 2 Pi_zz, 3 Pi_xy,
+    // 4 Pi_xz, 5 Pi_yz, 6-8 F^E, 9-11 e = u x B.
+    const T gm1 = T(a.gamma - 1.0), gam = T(a.gamma), two_nu = T(2.0 * a.nu), eta = T(a.eta);
+    double cfl = 0.0, bad = 0.0;
+    for (int x = tid; x < N; x += kThreads) {
+      cx<T> v[16];
+#pragma unroll
+      for (int f = 0; f < 16; ++f) v[f] = buf[f * BS + x];
+      cx<T> o[12];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        auto g = [&](int f) -> T { return h == 0 ? v[f].x : v[f].y; };
+        const T rho = g(0), mx = g(1), my = g(2), mz = g(3);
+        const T Bx = g(4), By = g(5), Bz = g(6), E = g(7);
+        const T Sxx = g(8), Syy = g(9), Sxy = g(10), Sxz = g(11), Syz = g(12);
+        const T Szz = -(Sxx + Syy);
+        const T Jx = g(13), Jy = g(14), Jz = g(15);
+        const T ir = T(1) / rho;
+        const T ux = mx * ir, uy = my * ir, uz = mz * ir;
+        const T B2 = Bx * Bx + By * By + Bz * Bz;
+        const T P = gm1 * (E - T(0.5) * (mx * ux + my * uy + mz * uz) - T(0.5) * B2);
+        const T Pt = P + T(0.5) * B2;
+        const T vr = two_nu * rho;
+        T out[12];
+        out[0] = mx * ux + Pt - Bx * Bx - vr * Sxx;
+        out[1] = my * uy + Pt - By * By - vr * Syy;
+        out[2] = mz * uz + Pt - Bz * Bz - vr * Szz;
+        out[3] = mx * uy - Bx * By - vr * Sxy;
+        out[4] = mx * uz - Bx * Bz - vr * Sxz;
+        out[5] = my * uz - By * Bz - vr * Syz;
+        const T uB = ux * Bx + uy * By + uz * Bz;
+        const T EP = E + Pt;
+        const T uSx = ux * Sxx + uy * Sxy + uz * Sxz;
+        const T uSy = ux * Sxy + uy * Syy + uz * Syz;
+        const T uSz = ux * Sxz + uy * Syz + uz * Szz;
+        out[6] = EP * ux - uB * Bx - vr * uSx - eta * (By * Jz - Bz * Jy);
+        out[7] = EP * uy - uB * By - vr * uSy - eta * (Bz * Jx - Bx * Jz);
+        out[8] = EP * uz - uB * Bz - vr * uSz - eta * (Bx * Jy - By * Jx);
+        out[9] = uy * Bz - uz * By;
+        out[10] = uz * Bx - ux * Bz;
+        out[11] = ux * By - uy * Bx;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+          if (h == 0) o[q].x = out[q];
+          else o[q].y = out[q];
+        }
+        const T umax = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
+        const double c = double(umax) + sqrt(double(gam * P + B2) / double(rho));
+        if (!(c <= cfl)) cfl = c;  // NaN propagates
+        bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) && finite_(By) &&
+                   finite_(Bz) && finite_(E);
+        bad += fin ? 0.0 : 1.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 12; ++q) buf[q * BS + x] = o[q];
+    }
+    // per-block CFL max and non-finite count (deterministic tree reduction)
+    __shared__ double s_red[kThreads];
+    const double cfl_b = block_reduce(cfl, true, s_red, tid);
+    const double bad_b = block_reduce(bad, false, s_red, tid);
+    if (tid == 0) {
+      a.partials[2 * (int64_t)p + 0] = cfl_b;
+      a.partials[2 * (int64_t)p + 1] = bad_b;
+    }
+  }
+
+  if constexpr (MODE == RM_XDIAG) {
+    // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8-10 J, 11 div B.
+    const T gm1 = T(a.gamma - 1.0), gam = T(a.gamma);
+    double q[kDiagQ];
+#pragma unroll
+    for (int i = 0; i < kDiagQ; ++i) q[i] = 0.0;
+    for (int x = tid; x < N; x += kThreads) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        auto g = [&](int f) -> double { const cx<T> v = buf[f * BS + x]; return double(h == 0 ? v.x : v.y); };
+        const double rho = g(0), mx = g(1), my = g(2), mz = g(3), Bx = g(4), By = g(5), Bz = g(6), E = g(7);
+        const double Jx = g(8), Jy = g(9), Jz = g(10), dB = g(11);
+        const double ux = mx / rho, uy = my / rho, uz = mz / rho;
+        const double B2 = Bx * Bx + By * By + Bz * Bz;
+        const double mu = mx * ux + my * uy + mz * uz;
+        const double P = double(gm1) * (E - 0.5 * mu - 0.5 * B2);
+        q[DQ_RHO] += rho;
+        q[DQ_MX] += mx;
+        q[DQ_MY] += my;
+        q[DQ_MZ] += mz;
+        q[DQ_EKIN] += 0.5 * mu;
+        q[DQ_EMAG] += 0.5 * B2;
+        q[DQ_P] += P;
+        q[DQ_E] += E;
+        q[DQ_HC] += ux * Bx + uy * By + uz * Bz;
+        q[DQ_UABS] += sqrt(ux * ux + uy * uy + uz * uz);
+        q[DQ_BABS] += sqrt(B2);
+        const double adb = fabs(dB);
+        if (!(adb <= q[DQ_DIVB_MAX])) q[DQ_DIVB_MAX] = adb;
+        const double c = fmax(fabs(ux), fmax(fabs(uy), fabs(uz))) + sqrt((double(gam) * P + B2) / rho);
+        if (!(c <= q[DQ_CFL_MAX])) q[DQ_CFL_MAX] = c;
+        const bool fin = isfinite(rho) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(Bx) &&
+                         isfinite(By) && isfinite(Bz) && isfinite(E);
+        q[DQ_NONFINITE] += fin ? 0.0 : 1.0;
+        q[DQ_J2] += Jx * Jx + Jy * Jy + Jz * Jz;
+      }
+    }
+    __shared__ double s_red[kThreads];
+    for (int i = 0; i < kDiagQ; ++i) {
+      const double r = block_reduce(q[i], i == DQ_DIVB_MAX || i == DQ_CFL_MAX, s_red, tid);
+      if (tid == 0) a.partials[(int64_t)p * kDiagQ + i] = r;
+    }
+    return;
+  }
+
+  if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
+    __syncthreads();
+    lds_fft<T, N, NB, kThreads, 1, BS, -1>(buf, stw, tid, nout);
+    // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
+    for (int e = tid; e < nout * NH; e += kThreads) {
+      const int fld = e / NH, k = e - (e / NH) * NH;
+      const cx<T> zk = buf[fld * BS + k];
+      const cx<T> zm = buf[fld * BS + (k == 0 ? 0 : N - k)];
+      const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+      const cx<T> x1 = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
+      st(a.out[fld], row0 * NH + k, x0);
+      st(a.out[fld], (row0 + 1) * NH + k, x1);
+    }
+  }
+}
+
+}  // namespace mhd

@@ -1,0 +1,31 @@
+// Per-grid-size kernel launchers, filled in by one translation unit per size
+// (mhd_inst.hip compiled with -DMHD_N=<n>).
+#pragma once
+
+#include "mhd_internal.h"
+
+namespace mhd {
+
+template <typename T>
+struct Kern {
+  int n = 0;
+  int col_width = 0;  // columns per workgroup of the column passes
+  void (*col_inv)(const ColArgs<T>&, dim3, hipStream_t) = nullptr;
+  void (*col_fwd)(const ColArgs<T>&, dim3, hipStream_t) = nullptr;
+  void (*rhs)(const RhsArgs<T>&, dim3, hipStream_t) = nullptr;
+  void (*row)(int mode, const RowArgs<T>&, dim3, hipStream_t) = nullptr;
+};
+
+struct Registry {
+  Kern<float> f32[1025];
+  Kern<double> f64[1025];
+};
+
+Registry& registry();
+
+#define MHD_SIZES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+#define MHD_DECLARE_REGISTER(NN) void register_##NN(Registry&);
+MHD_SIZES(MHD_DECLARE_REGISTER)
+#undef MHD_DECLARE_REGISTER
+
+}  // namespace mhd

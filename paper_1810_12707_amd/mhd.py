@@ -1,0 +1,266 @@
+"""Python binding of libmhd (include/mhd.h): argument marshalling only.
+
+Every function keeps the C name and forwards to the HIP library; torch is used
+only to own device memory (the workspace and field tensors) and to supply the
+stream.  There is no fallback: if libmhd.so is missing or fails to load, the
+import of this module's functions raises.
+
+Field tensors are (8, n, n, n) with axes (field, z, y, x), field order
+rho, m_x, m_y, m_z, B_x, B_y, B_z, E, dtype float64 or float32, contiguous,
+on the GPU the solver was created on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "_lib", "libmhd.so")
+
+MHD_OK, MHD_E_ARG, MHD_E_SIZE, MHD_E_WORKSPACE, MHD_E_HIP, MHD_E_NONFINITE, MHD_E_CFL, MHD_E_STATE = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+MHD_FP64, MHD_FP32 = 0, 1
+MHD_FLAG_CHECK_CFL = 1
+
+EXPORTED = (
+    "mhd_supported_size", "mhd_workspace_bytes", "mhd_init", "mhd_set_state", "mhd_get_state",
+    "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_destroy",
+    "mhd_status_string", "mhd_last_error",
+)
+
+
+class mhd_params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("reserved", ctypes.c_int32), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
+        ("eta", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+    ]
+
+
+class mhd_diag(ctypes.Structure):
+    _fields_ = [
+        ("t", ctypes.c_double), ("step", ctypes.c_int64), ("mass", ctypes.c_double),
+        ("mom", ctypes.c_double * 3), ("e_kin", ctypes.c_double), ("e_mag", ctypes.c_double),
+        ("e_int", ctypes.c_double), ("e_tot", ctypes.c_double), ("h_cross", ctypes.c_double),
+        ("h_mag", ctypes.c_double), ("divb_rms", ctypes.c_double), ("divb_max", ctypes.c_double),
+        ("divb_rel", ctypes.c_double), ("j_rms", ctypes.c_double), ("dt_cfl", ctypes.c_double),
+        ("c_s", ctypes.c_double), ("v_a", ctypes.c_double), ("mach_s", ctypes.c_double),
+        ("mach_a", ctypes.c_double), ("nonfinite", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if name == "mom" else v
+        return d
+
+
+class MHDError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmhd.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise ImportError(f"libmhd.so not built at {LIBPATH}: run __graft_entry__.build() "
+                              "or python -m paper_1810_12707_amd.build_lib")
+        L = ctypes.CDLL(LIBPATH)
+        vp, P = ctypes.c_void_p, ctypes.POINTER(mhd_params)
+        L.mhd_supported_size.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.mhd_workspace_bytes.argtypes = [P]
+        L.mhd_workspace_bytes.restype = ctypes.c_size_t
+        L.mhd_init.argtypes = [P, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.mhd_set_state.argtypes = [vp, vp, ctypes.c_int32]
+        L.mhd_get_state.argtypes = [vp, vp, ctypes.c_int32]
+        L.mhd_rhs.argtypes = [vp, vp, vp, ctypes.c_int32]
+        L.mhd_step.argtypes = [vp, ctypes.c_int32]
+        L.mhd_diagnostics.argtypes = [vp, ctypes.POINTER(mhd_diag)]
+        L.mhd_fft3d.argtypes = [vp, ctypes.c_int32, vp, vp]
+        L.mhd_spectrum_size.argtypes = [ctypes.c_int32]
+        L.mhd_spectrum_size.restype = ctypes.c_int64
+        L.mhd_destroy.argtypes = [vp]
+        L.mhd_status_string.argtypes = [ctypes.c_int]
+        L.mhd_status_string.restype = ctypes.c_char_p
+        L.mhd_last_error.argtypes = [vp]
+        L.mhd_last_error.restype = ctypes.c_char_p
+        for name in ("mhd_supported_size", "mhd_init", "mhd_set_state", "mhd_get_state", "mhd_rhs",
+                     "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return lib().mhd_status_string(int(status)).decode()
+
+
+def make_params(n, precision=MHD_FP32, gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=1e-3, cfl=0.1, flags=0) -> mhd_params:
+    return mhd_params(int(n), int(precision), int(flags), 0, float(gamma), float(nu), float(eta), float(dt),
+                      float(cfl))
+
+
+# ---------------------------------------------------------------- same-name wrappers
+
+def mhd_supported_size(n: int, precision: int) -> bool:
+    return bool(lib().mhd_supported_size(int(n), int(precision)))
+
+
+def mhd_workspace_bytes(p: mhd_params) -> int:
+    return int(lib().mhd_workspace_bytes(ctypes.byref(p)))
+
+
+def mhd_spectrum_size(n: int) -> int:
+    return int(lib().mhd_spectrum_size(int(n)))
+
+
+def _dtype_code(t) -> int:
+    import torch
+
+    if t.dtype == torch.float64:
+        return MHD_FP64
+    if t.dtype == torch.float32:
+        return MHD_FP32
+    raise TypeError(f"fields must be float32 or float64, got {t.dtype}")
+
+
+def _check_fields(t, n: int):
+    if not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (8, n, n, n):
+        raise ValueError(f"expected a contiguous CUDA tensor of shape (8, {n}, {n}, {n}), got "
+                         f"{tuple(t.shape)} on {t.device}")
+
+
+def _rc(rc: int, what: str, ctx=None):
+    if rc != MHD_OK:
+        msg = what
+        if ctx is not None and rc == MHD_E_HIP:
+            msg += " [" + lib().mhd_last_error(ctx).decode() + "]"
+        raise MHDError(rc, msg)
+
+
+def mhd_init(p: mhd_params, workspace, stream_handle: int):
+    """workspace: uint8 CUDA tensor of >= mhd_workspace_bytes(p) bytes."""
+    ctx = ctypes.c_void_p()
+    rc = lib().mhd_init(ctypes.byref(p), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                        ctypes.c_void_p(stream_handle), ctypes.byref(ctx))
+    _rc(rc, "mhd_init")
+    return ctx
+
+
+def mhd_set_state(ctx, fields):
+    _rc(lib().mhd_set_state(ctx, ctypes.c_void_p(fields.data_ptr()), _dtype_code(fields)), "mhd_set_state", ctx)
+
+
+def mhd_get_state(ctx, out):
+    _rc(lib().mhd_get_state(ctx, ctypes.c_void_p(out.data_ptr()), _dtype_code(out)), "mhd_get_state", ctx)
+
+
+def mhd_rhs(ctx, fields_in, rhs_out):
+    if fields_in.dtype != rhs_out.dtype:
+        raise TypeError("fields_in and rhs_out must share a dtype")
+    _rc(lib().mhd_rhs(ctx, ctypes.c_void_p(fields_in.data_ptr()), ctypes.c_void_p(rhs_out.data_ptr()),
+                      _dtype_code(fields_in)), "mhd_rhs", ctx)
+
+
+def mhd_step(ctx, nsteps: int):
+    _rc(lib().mhd_step(ctx, int(nsteps)), "mhd_step", ctx)
+
+
+def mhd_diagnostics(ctx) -> tuple[int, dict]:
+    d = mhd_diag()
+    rc = lib().mhd_diagnostics(ctx, ctypes.byref(d))
+    if rc not in (MHD_OK, MHD_E_NONFINITE, MHD_E_CFL):
+        _rc(rc, "mhd_diagnostics", ctx)
+    return rc, d.as_dict()
+
+
+def mhd_fft3d(ctx, direction: int, x_in, x_out):
+    _rc(lib().mhd_fft3d(ctx, int(direction), ctypes.c_void_p(x_in.data_ptr()), ctypes.c_void_p(x_out.data_ptr())),
+        "mhd_fft3d", ctx)
+
+
+def mhd_destroy(ctx):
+    lib().mhd_destroy(ctx)
+
+
+# ---------------------------------------------------------------- convenience owner
+
+class Solver:
+    """Owns one context, its workspace tensor and the stream it runs on."""
+
+    def __init__(self, n, precision="fp32", gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=1e-3, cfl=0.1,
+                 flags=0, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.n = int(n)
+        self.precision = MHD_FP32 if precision in ("fp32", MHD_FP32) else MHD_FP64
+        self.params = make_params(n, self.precision, gamma, nu, eta, dt, cfl, flags)
+        nbytes = mhd_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise MHDError(MHD_E_ARG if mhd_supported_size(n, self.precision) else MHD_E_SIZE, "mhd_workspace_bytes")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.ctx = mhd_init(self.params, self._ws, self.stream.cuda_stream)
+        self.real_dtype = torch.float32 if self.precision == MHD_FP32 else torch.float64
+
+    @property
+    def spectrum_size(self) -> int:
+        return mhd_spectrum_size(self.n)
+
+    def set_state(self, U):
+        _check_fields(U, self.n)
+        mhd_set_state(self.ctx, U)
+
+    def get_state(self, dtype=None):
+        out = self.torch.empty((8, self.n, self.n, self.n), dtype=dtype or self.torch.float64, device=self.device)
+        mhd_get_state(self.ctx, out)
+        return out
+
+    def rhs(self, U):
+        _check_fields(U, self.n)
+        out = self.torch.empty_like(U)
+        mhd_rhs(self.ctx, U, out)
+        return out
+
+    def step(self, nsteps=1):
+        mhd_step(self.ctx, nsteps)
+
+    def diagnostics(self) -> tuple[int, dict]:
+        return mhd_diagnostics(self.ctx)
+
+    def fft_forward(self, f):
+        """Real n^3 field (working precision) -> compact spectrum, complex view."""
+        n = self.n
+        assert f.is_cuda and f.is_contiguous() and tuple(f.shape) == (n, n, n) and f.dtype == self.real_dtype
+        out = self.torch.empty(2 * self.spectrum_size, dtype=self.real_dtype, device=self.device)
+        mhd_fft3d(self.ctx, -1, f, out)
+        return out
+
+    def fft_inverse(self, spec):
+        n = self.n
+        assert spec.is_cuda and spec.is_contiguous() and spec.numel() == 2 * self.spectrum_size
+        out = self.torch.empty((n, n, n), dtype=self.real_dtype, device=self.device)
+        mhd_fft3d(self.ctx, 1, spec, out)
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            mhd_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,100 @@
+"""Host-side checks of the C-ABI library (no GPU needed, no compute calls):
+it loads, exports every function include/mhd.h declares, validates
+parameters, sizes its workspace, and rejects bad workspaces before touching
+the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_1810_12707_amd import mhd
+
+    if not os.path.exists(mhd.LIBPATH):
+        pytest.fail("libmhd.so is not built (run __graft_entry__.build())")
+    mhd.lib()
+    return mhd
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mhd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(M):
+    names = declared_functions()
+    assert len(names) >= 13
+    L = M.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(M.EXPORTED) == names
+
+
+def test_status_strings(M):
+    for code in range(-7, 1):
+        assert M.status_string(code) and M.status_string(code) != "unknown status"
+    assert M.status_string(-99) == "unknown status"
+
+
+def test_supported_sizes(M):
+    for n in (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512):
+        assert M.mhd_supported_size(n, M.MHD_FP64) and M.mhd_supported_size(n, M.MHD_FP32)
+    for n in (768, 1024):
+        assert M.mhd_supported_size(n, M.MHD_FP32) and not M.mhd_supported_size(n, M.MHD_FP64)
+    for n in (0, 7, 10, 20, 100, 2048):
+        assert not M.mhd_supported_size(n, M.MHD_FP32)
+    assert not M.mhd_supported_size(32, 5)
+
+
+def test_workspace_sizing(M):
+    def ws(n, prec):
+        return M.mhd_workspace_bytes(M.make_params(n, prec))
+
+    # grows with n^3 and doubles (to within the small fixed parts) from FP32 to FP64
+    assert ws(64, M.MHD_FP32) > 7 * ws(32, M.MHD_FP32)
+    r = ws(128, M.MHD_FP64) / ws(128, M.MHD_FP32)
+    assert 1.9 < r < 2.01
+    # 512^3 FP32 with all fields resident fits easily in one MI355X (288 GB)
+    assert ws(512, M.MHD_FP32) < 20e9
+    assert ws(1024, M.MHD_FP32) < 150e9
+    assert M.mhd_spectrum_size(32) == 21 * 21 * 11
+
+
+@pytest.mark.parametrize("field,value", [("gamma", 1.0), ("nu", -1.0), ("eta", -0.1), ("dt", 0.0), ("cfl", 0.0),
+                                         ("dt", float("nan")), ("precision", 7), ("reserved", 1)])
+def test_invalid_params_rejected(M, field, value):
+    p = M.make_params(32)
+    setattr(p, field, value)
+    assert M.mhd_workspace_bytes(p) == 0
+    ctx = ctypes.c_void_p()
+    assert M.lib().mhd_init(ctypes.byref(p), ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(ctx)) == M.MHD_E_ARG
+
+
+def test_bad_size_and_workspace(M):
+    L = M.lib()
+    ctx = ctypes.c_void_p()
+    assert L.mhd_init(ctypes.byref(M.make_params(20)), None, 0, None, ctypes.byref(ctx)) == M.MHD_E_SIZE
+    assert L.mhd_init(ctypes.byref(M.make_params(1024, M.MHD_FP64)), None, 0, None,
+                      ctypes.byref(ctx)) == M.MHD_E_SIZE
+    p = M.make_params(32)
+    need = M.mhd_workspace_bytes(p)
+    assert L.mhd_init(ctypes.byref(p), None, need, None, ctypes.byref(ctx)) == M.MHD_E_WORKSPACE
+    assert L.mhd_init(ctypes.byref(p), ctypes.c_void_p(4096), need - 1, None, ctypes.byref(ctx)) == M.MHD_E_WORKSPACE
+    assert L.mhd_init(ctypes.byref(p), ctypes.c_void_p(4096 + 8), need, None, ctypes.byref(ctx)) == M.MHD_E_WORKSPACE
+    assert L.mhd_init(ctypes.byref(p), ctypes.c_void_p(4096), need, None, None) == M.MHD_E_ARG
+
+
+def test_null_context_calls(M):
+    L = M.lib()
+    assert L.mhd_step(None, 1) == M.MHD_E_ARG
+    assert L.mhd_set_state(None, None, 0) == M.MHD_E_ARG
+    assert L.mhd_rhs(None, None, None, 0) == M.MHD_E_ARG
+    assert L.mhd_diagnostics(None, None) == M.MHD_E_ARG
+    assert L.mhd_fft3d(None, 1, None, None) == M.MHD_E_ARG
+    assert L.mhd_last_error(None) == b""
