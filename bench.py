@@ -1,0 +1,289 @@
+#!/usr/bin/env python
+"""Throughput of the pseudo-spectral compressible-MHD step on one MI355X.
+
+One step = one pass of the hot path: phase A (u^ = D F[m/rho]), phase B
+(strain, current, all real-space fluxes, forward transforms, divergence and
+curl, resistive term, AB2 update) and the per-step FP64 CFL / non-finite
+reduction; the full FP64 diagnostics pass runs every 10 steps inside the timed
+region.  Inputs are resident in HBM before timing starts.
+
+Default workload: 256^3 random-phase turbulence (solenoidal u with E(k) ~ k^-2
+in shells 1-8, Mach 0.3; B rms 0.1 in shells 1-4; rho = 1 +- 1%), FP32,
+nu = eta = 2e-3, dt from CFL 0.1.  A secondary 512^3 ABC-dynamo line
+(nu = eta = 1e-3) is measured the same way and reported under "secondary".
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+PASS_NAMES = ("zinv_a", "yinv_a", "xa", "yfwd_a", "zfwd_a", "zinv_b", "yinv_b", "xb", "yfwd_b", "zrhs", "reduce")
+PASS_KERNELS = {
+    "zinv_a": "k_col<float,N,1> (inverse z, 4 fields)",
+    "yinv_a": "k_col<float,N,1> (inverse y, 4 fields)",
+    "xa": "k_row<float,N,RM_XA>",
+    "yfwd_a": "k_col<float,N,-1> (forward y, 3 fields)",
+    "zfwd_a": "k_col<float,N,-1> (forward z, 3 fields)",
+    "zinv_b": "k_col<float,N,1> (inverse z, 12 outputs)",
+    "yinv_b": "k_col<float,N,1> (inverse y, 12 fields)",
+    "xb": "k_row<float,N,RM_XB>",
+    "yfwd_b": "k_col<float,N,-1> (forward y, 12 fields)",
+    "zrhs": "k_zfwd_rhs<float,N>",
+    "reduce": "k_reduce",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_case(name: str):
+    from paper_1810_12707_amd import inputs as I
+
+    if name == "turb256":
+        return I.config_turb256(256)
+    if name == "abc512":
+        return I.config_dynamo512(512)
+    if name.startswith("turb"):
+        return I.random_turbulence(int(name[4:]), name=name)
+    if name.startswith("abc"):
+        return I.abc_dynamo(int(name[3:]), 1e-3, 1e-3, None, 200, name=name)
+    raise ValueError(name)
+
+
+def describe(case) -> str:
+    n = case.n
+    if case.name.startswith("turb"):
+        return (f"{n}^3 random-phase MHD turbulence, FP32: solenoidal u E(k)~k^-2 shells 1-8 Mach 0.3, "
+                f"B rms 0.1 shells 1-4, rho=1+-1%, gamma=5/3, nu=eta={case.nu:g}, dt={case.dt:.3e} (CFL 0.1), "
+                "AB2, 2/3 dealiasing")
+    return (f"{n}^3 ABC-flow dynamo start, FP32: rho=1, ABC u (A=B=C=1, k=1), B rms 1e-3 shells 1-4, Mach 0.1, "
+            f"gamma=5/3, nu=eta={case.nu:g}, dt={case.dt:.3e} (CFL 0.1), AB2, 2/3 dealiasing")
+
+
+def run_gpu(case, steps: int, warmup: int, diag_every: int = 10, with_fp64_error: bool = True):
+    import numpy as np
+    import torch
+
+    from paper_1810_12707_amd.mhd import Solver
+
+    n = case.n
+    dev = torch.device("cuda:0")
+    U64 = torch.from_numpy(case.U).to(dev)
+    S = Solver(n, precision="fp32", gamma=case.gamma, nu=case.nu, eta=case.eta, dt=case.dt, device=dev)
+    S.set_state(U64)
+    for _ in range(warmup):
+        S.step(1)
+    torch.cuda.synchronize()
+    S.profile(True)
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    rc_diag = 0
+    for k in range(steps):
+        S.step(1)
+        if diag_every and (k + 1) % diag_every == 0:
+            rc_diag, _ = S.diagnostics()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    prof = S.profile_read()
+    S.profile(False)
+    rc_end, diag = S.diagnostics()
+    step_bytes = S.step_bytes
+    ws_bytes = S.workspace.numel()
+    err = None
+    if with_fp64_error:
+        # same start, same number of steps, FP64 path on the GPU
+        Uf32 = S.get_state(torch.float64)
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+        D = Solver(n, precision="fp64", gamma=case.gamma, nu=case.nu, eta=case.eta, dt=case.dt, device=dev)
+        D.set_state(U64)
+        D.step(warmup + steps)
+        Uf64 = D.get_state(torch.float64)
+        err = {name: float(torch.linalg.vector_norm(Uf32[f] - Uf64[f]) / torch.linalg.vector_norm(Uf64[f]))
+               for f, name in enumerate(("rho", "m_x", "m_y", "m_z", "B_x", "B_y", "B_z", "E"))}
+        D.close()
+        del D, Uf32, Uf64
+    else:
+        S.close()
+        del S
+    del U64
+    torch.cuda.empty_cache()
+    return {"ms": ms, "wall_s": wall, "prof": prof, "diag": diag, "rc": (rc_diag, rc_end), "step_bytes": step_bytes,
+            "ws_bytes": ws_bytes, "err_vs_fp64": err}
+
+
+def roofline_from(prof: dict, traffic: dict | None):
+    passes = {k: v for k, v in prof.items() if k in PASS_NAMES and v["launches"] > 0}
+    dom = max(passes, key=lambda k: passes[k]["ms"])
+    p = passes[dom]
+    per_launch_bytes = p["bytes"] / p["launches"]
+    per_launch_ms = p["ms"] / p["launches"]
+    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    t = None
+    if traffic and dom in traffic:
+        t = traffic[dom]
+    return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": t, "kernel": PASS_KERNELS[dom],
+                 "bytes_per_launch": per_launch_bytes, "ms_per_launch": round(per_launch_ms, 5)}
+
+
+def pass_table(prof: dict, steps: int):
+    out = {}
+    for k in PASS_NAMES:
+        v = prof[k]
+        if v["launches"] == 0:
+            continue
+        gbs = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
+        out[k] = {"ms_per_step": round(v["ms"] / steps, 5), "GBps": round(gbs, 1) if gbs else None,
+                  "frac_hbm": round(gbs / HBM_PEAK_GBS, 4) if gbs else None}
+    return out
+
+
+def load_traffic(n: int):
+    """HBM bytes per launch measured by rocprofv3 counters, if recorded for the
+    current kernel sources (profiles/traffic_<n>.json carries a source hash)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{n}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(ROOT, "paper_1810_12707_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1810_12707_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n_sample: int = 128):
+    """The FP64 CPU oracle (as it stands) on one AB2 step of the same
+    random-turbulence recipe at n_sample^3, scaled to grid-point-steps/s."""
+    from oracle import oracle as O
+    from paper_1810_12707_amd import inputs as I
+
+    c = I.random_turbulence(n_sample)
+    t0 = time.perf_counter()
+    O.run(c.U, 1, c.dt, c.gamma, c.nu, c.eta)
+    dt = time.perf_counter() - t0
+    return {"value": round(n_sample ** 3 / dt, 1), "unit": "grid-point-steps/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"1 AB2 step (RHS + update) of the random-turbulence recipe at {n_sample}^3, FP64, "
+                      f"{dt:.2f} s; the 256^3 step would take minutes"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="turb256", help="turb256 (default), abc512, turbN, abcN")
+    ap.add_argument("--secondary", default="abc512", help="second workload reported alongside ('' = none)")
+    ap.add_argument("--secondary-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-error", action="store_true")
+    a = ap.parse_args(argv)
+
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+
+    log(f"[bench] building input {a.config}")
+    case = make_case(a.config)
+    log(f"[bench] n={case.n} dt={case.dt:.3e}; warmup {a.warmup}, timed {a.steps} steps")
+    r = run_gpu(case, a.steps, a.warmup, with_fp64_error=not a.no_fp64_error)
+    n = case.n
+    sec = r["ms"] * 1e-3
+    value = n ** 3 * a.steps / sec
+    dom, roof = roofline_from(r["prof"], load_traffic(n))
+    step_gbs = r["step_bytes"] / (sec / a.steps) / 1e9
+    log(f"[bench] {r['ms'] / a.steps:.4f} ms/step, {value:.4e} pt-steps/s; dominant {dom} {roof['achieved']} GB/s")
+    workload = describe(case)
+    del case
+
+    secondary = None
+    if a.secondary:
+        log(f"[bench] secondary workload {a.secondary}")
+        c2 = make_case(a.secondary)
+        r2 = run_gpu(c2, a.secondary_steps, 3, with_fp64_error=not a.no_fp64_error)
+        s2 = r2["ms"] * 1e-3
+        dom2, roof2 = roofline_from(r2["prof"], load_traffic(c2.n))
+        secondary = {
+            "workload": describe(c2), "value": c2.n ** 3 * a.secondary_steps / s2, "unit": "grid-point-steps/s",
+            "ms_per_step": round(r2["ms"] / a.secondary_steps, 4), "steps": a.secondary_steps,
+            "roofline": roof2,
+            "step_hbm": {"alg_bytes_per_step": r2["step_bytes"],
+                         "GBps": round(r2["step_bytes"] / (s2 / a.secondary_steps) / 1e9, 1),
+                         "frac": round(r2["step_bytes"] / (s2 / a.secondary_steps) / 1e9 / HBM_PEAK_GBS, 4)},
+            "passes": pass_table(r2["prof"], a.secondary_steps),
+            "err_vs_fp64": r2["err_vs_fp64"], "status": r2["rc"],
+        }
+        log(f"[bench] secondary {secondary['ms_per_step']} ms/step")
+        del c2
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        cpu = cpu_baseline()
+        log(f"[bench] cpu {cpu['value']:.3e} pt-steps/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "grid-point-steps/s",
+        "value": round(value, 1),
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(r["ms"] / a.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "grid": n, "global_batch": 1,
+                   "parallelism": "none (1 GPU)", "diagnostics_every": 10},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "step_hbm": {"alg_bytes_per_step": r["step_bytes"], "GBps": round(step_gbs, 1),
+                     "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "passes": pass_table(r["prof"], a.steps),
+        "err_vs_fp64": r["err_vs_fp64"],
+        "mixed_path": None,
+        "status": r["rc"],
+        "wall_s": round(r["wall_s"], 4),
+        "secondary": secondary,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -152,6 +152,32 @@ int mhd_fft3d(mhd_ctx* ctx, int32_t dir, const void* d_in, void* d_out);
 /* Number of complex values of one compact spectrum, (2K+1)^2 (K+1). */
 int64_t mhd_spectrum_size(int32_t n);
 
+/* Launch classes of one step, for mhd_profile_read.  Suffix _A: phase A
+ * (u^ = D F[m/rho]); _B: phase B (fluxes and update). */
+enum {
+    MHD_PASS_ZINV_A = 0, MHD_PASS_YINV_A, MHD_PASS_XA, MHD_PASS_YFWD_A, MHD_PASS_ZFWD_A,
+    MHD_PASS_ZINV_B, MHD_PASS_YINV_B, MHD_PASS_XB, MHD_PASS_YFWD_B, MHD_PASS_ZRHS,
+    MHD_PASS_REDUCE, MHD_PASS_COUNT
+};
+
+/* Benchmark hook (not physics): enable = 1 clears the counters and brackets
+ * every later kernel launch of mhd_step with a pair of HIP events on the
+ * context's stream (at most 4096 launches are recorded; later ones are
+ * counted as dropped); enable = 0 stops recording.  Creates its events on
+ * first use (no device memory). */
+int mhd_profile(mhd_ctx* ctx, int32_t enable);
+
+/* Synchronises the stream and writes, per launch class (MHD_PASS_*), the
+ * summed kernel time in milliseconds, the number of launches timed and the
+ * summed algorithmic HBM bytes of those launches (each input and output
+ * array counted once).  Any pointer may be NULL.  Returns the number of
+ * dropped launches through *dropped when non-NULL. */
+int mhd_profile_read(mhd_ctx* ctx, double* ms, int64_t* launches, double* bytes, int64_t* dropped);
+
+/* Algorithmic HBM bytes of one mhd_step of this context (sum over its
+ * launches, each array read or written once), or 0 for a null context. */
+double mhd_step_bytes(const mhd_ctx* ctx);
+
 /* Releases the host-side context (not the caller's workspace). */
 int mhd_destroy(mhd_ctx* ctx);
 

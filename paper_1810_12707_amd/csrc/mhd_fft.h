@@ -138,8 +138,23 @@ template <int N> constexpr bool plan_ok() {
   return prod == N;
 }
 
+// Lane -> (sequence b, butterfly j) assignment of a pass with NBF butterflies
+// per sequence: MAP 0 puts the batch fastest (column tiles: lanes touch
+// adjacent columns), MAP 1 the butterfly fastest (rows: lanes touch adjacent
+// elements of one sequence).
+template <int NB, int NBF, int MAP>
+__device__ __forceinline__ void lane_map(int w, int& b, int& j) {
+  if constexpr (MAP == 0) {
+    b = w % NB;
+    j = w / NB;
+  } else {
+    b = w / NBF;
+    j = w % NBF;
+  }
+}
+
 // One Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P>
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   constexpr int R = Plan<N>::r[P];
   constexpr int NS = plan_ns<N>(P);
@@ -150,7 +165,8 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
 #pragma unroll
   for (int i = 0; i < CNT; ++i) {
     const int w = tid + i * NT;
-    const int b = w % NB, j = w / NB;
+    int b, j;
+    lane_map<NB, NBF, MAP>(w, b, j);
     if ((TOT % NT == 0 || w < TOT) && b < b_act) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = buf[b * BS + (j + r * NBF) * ES];
@@ -169,7 +185,8 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
 #pragma unroll
   for (int i = 0; i < CNT; ++i) {
     const int w = tid + i * NT;
-    const int b = w % NB, j = w / NB;
+    int b, j;
+    lane_map<NB, NBF, MAP>(w, b, j);
     if ((TOT % NT == 0 || w < TOT) && b < b_act) {
       const int k = j % NS;
       const int d = (j / NS) * NS * R + k;
@@ -180,13 +197,116 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
   __syncthreads();
 }
 
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P = 0>
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int P = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   static_assert(plan_ok<N>(), "radix plan does not multiply to N");
   if constexpr (P < Plan<N>::np) {
-    fft_pass<T, N, NB, NT, ES, BS, S, P>(buf, tw, tid, b_act);
-    lds_fft<T, N, NB, NT, ES, BS, S, P + 1>(buf, tw, tid, b_act);
+    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP>(buf, tw, tid, b_act);
+    lds_fft<T, N, NB, NT, ES, BS, S, MAP, P + 1>(buf, tw, tid, b_act);
   }
+}
+
+// Register-ended FFT: the first pass takes its inputs from load(b, pos)
+// (global memory) and the last pass hands its outputs to
+// store(i, r, b, pos, value) from registers; only the passes in between go
+// through LDS.  load() is called for all CNT*R elements of a thread before any
+// arithmetic, so their memory requests are in flight together.  For one-pass
+// plans the inputs go straight from load() through the DFT to store().
+// The LDS buffer may be reused after this returns only past a __syncthreads().
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int P>
+__device__ __forceinline__ void fft_mid_passes(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
+  if constexpr (P < Plan<N>::np - 1) {
+    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP>(buf, tw, tid, b_act);
+    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, P + 1>(buf, tw, tid, b_act);
+  }
+}
+
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, class Load, class Store>
+__device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Load&& load,
+                                        Store&& store) {
+  static_assert(plan_ok<N>(), "radix plan does not multiply to N");
+  constexpr int NP = Plan<N>::np;
+  {
+    constexpr int R = Plan<N>::r[0];
+    constexpr int NBF = N / R;
+    constexpr int TOT = NB * NBF;
+    constexpr int CNT = (TOT + NT - 1) / NT;
+    cx<T> v[CNT][R];
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) {
+      const int w = tid + i * NT;
+      int b, j;
+      lane_map<NB, NBF, MAP>(w, b, j);
+      const bool ok = (TOT % NT == 0 || w < TOT) && b < b_act;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = ok ? load(b, j + r * NBF) : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) {
+      const int w = tid + i * NT;
+      int b, j;
+      lane_map<NB, NBF, MAP>(w, b, j);
+      if ((TOT % NT == 0 || w < TOT) && b < b_act) {
+        dft<R, S>(v[i]);
+        if constexpr (NP == 1) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) store(i, r, b, r, v[i][r]);
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) buf[b * BS + (j * R + r) * ES] = v[i][r];
+        }
+      }
+    }
+    if constexpr (NP == 1) return;
+    __syncthreads();
+  }
+  if constexpr (NP > 1) {
+    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, 1>(buf, tw, tid, b_act);
+    constexpr int PL = NP - 1;
+    constexpr int R = Plan<N>::r[PL];
+    constexpr int NS = plan_ns<N>(PL);  // = N / R
+    constexpr int NBF = N / R;
+    constexpr int TOT = NB * NBF;
+    constexpr int CNT = (TOT + NT - 1) / NT;
+#pragma unroll
+    for (int i = 0; i < CNT; ++i) {
+      const int w = tid + i * NT;
+      int b, j;
+      lane_map<NB, NBF, MAP>(w, b, j);
+      if ((TOT % NT == 0 || w < TOT) && b < b_act) {
+        cx<T> v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = buf[b * BS + (j + r * NBF) * ES];
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const cx<T> t = tw[j * r];  // k = j mod NS = j; index k r N/(NS R) = j r
+          v[r] = (S < 0) ? cmul(v[r], t) : cmulc(v[r], t);
+        }
+        dft<R, S>(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) store(i, r, b, j + r * NS, v[r]);
+      }
+    }
+  }
+}
+
+// Per-thread shape of the last pass of fft_reg (for callers that keep its
+// outputs in registers).
+template <int N, int NB, int NT> struct LastPass {
+  static constexpr int R = Plan<N>::r[Plan<N>::np - 1];
+  static constexpr int NBF = N / R;
+  static constexpr int TOT = NB * NBF;
+  static constexpr int CNT = (TOT + NT - 1) / NT;
+};
+
+// Workgroup id remap for gfx950's eight XCDs.  Workgroups are handed out
+// round-robin (id w runs on XCD w mod 8); the returned logical id makes each
+// XCD own one contiguous range, so logically adjacent workgroups share an L2.
+__device__ __forceinline__ int xcd_remap(int w, int total) {
+  constexpr int X = 8;
+  const int per = total / X, rem = total % X;
+  const int xcd = w % X, slot = w / X;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
 }  // namespace mhd

@@ -14,6 +14,7 @@
 #include <new>
 #include <type_traits>
 #include <string>
+#include <vector>
 
 #include "../../include/mhd.h"
 #include "mhd_internal.h"
@@ -213,6 +214,13 @@ struct mhd_ctx {
   int64_t step;
   double t;
   std::string last_err;
+  // benchmark timing (mhd_profile)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev;  // 2 per recorded launch
+  std::vector<int> rec_cls;
+  std::vector<double> rec_bytes;
+  int nrec = 0;
+  int64_t dropped = 0;
 };
 
 namespace {
@@ -270,6 +278,43 @@ struct Engine {
   double* status() const { return reinterpret_cast<double*>(c->ws + c->L.status); }
   double* res() const { return reinterpret_cast<double*>(c->ws + c->L.res); }
 
+  // Algorithmic HBM bytes of one launch: each array read or written once.
+  double cbytes(double n_sc, double n_iz, double n_iy) const {
+    return (n_sc * (double)g.sc + n_iz * (double)g.iz + n_iy * (double)g.iy) * 2.0 * sizeof(T);
+  }
+  double class_bytes(int cls) const {
+    switch (cls) {
+      case MHD_PASS_ZINV_A: return cbytes(4, 4, 0);
+      case MHD_PASS_YINV_A: return cbytes(0, 4, 4);
+      case MHD_PASS_XA: return cbytes(0, 0, 7);
+      case MHD_PASS_YFWD_A: return cbytes(0, 3, 3);
+      case MHD_PASS_ZFWD_A: return cbytes(3, 3, 0);
+      case MHD_PASS_ZINV_B: return cbytes(7, 12, 0);
+      case MHD_PASS_YINV_B: return cbytes(0, 12, 12);
+      case MHD_PASS_XB: return cbytes(0, 0, 28) + (double)g.n * g.n * sizeof(double);
+      case MHD_PASS_YFWD_B: return cbytes(0, 12, 12);
+      case MHD_PASS_ZRHS: return cbytes(32, 12, 0);
+      case MHD_PASS_REDUCE: return (double)g.n * g.n * sizeof(double);
+      default: return 0.0;
+    }
+  }
+
+  // Runs `launch`; while profiling, brackets it with a pair of events.
+  template <typename F>
+  void timed(int cls, F&& launch) {
+    if (c->prof_on && c->nrec < (int)c->rec_cls.size()) {
+      const int r = c->nrec++;
+      hipEventRecord(c->ev[2 * r], c->stream);
+      launch();
+      hipEventRecord(c->ev[2 * r + 1], c->stream);
+      c->rec_cls[r] = cls;
+      c->rec_bytes[r] = class_bytes(cls);
+    } else {
+      if (c->prof_on) ++c->dropped;
+      launch();
+    }
+  }
+
   int ztiles() const { return (int)((g.nb * g.nh + k.col_width - 1) / k.col_width); }
   int ytiles() const { return (g.nh + k.col_width - 1) / k.col_width; }
 
@@ -292,7 +337,7 @@ struct Engine {
       a.spec[f] = specs[f];
     }
     const bool z = (kind == PK_ZINV || kind == PK_ZFWD);
-    dim3 grid(z ? ztiles() : g.n * ytiles(), nout);
+    dim3 grid((unsigned)((z ? ztiles() : g.n * ytiles()) * nout));
     if (kind == PK_ZINV || kind == PK_YINV) k.col_inv(a, grid, c->stream);
     else k.col_fwd(a, grid, c->stream);
   }
@@ -317,6 +362,16 @@ struct Engine {
 
   dim3 row_grid() const { return dim3((unsigned)((int64_t)g.n * g.n / 2)); }
 
+  // Row passes address consecutive I_y slots from a first slot and a stride.
+  void set_in(RowArgs<T>& r, int first_slot) const {
+    r.in0 = iy(first_slot);
+    r.in_stride = g.iy;
+  }
+  void set_out(RowArgs<T>& r, int first_slot) const {
+    r.out0 = iy(first_slot);
+    r.out_stride = g.iy;
+  }
+
   double inv_n3() const { return 1.0 / (double)g.n3; }
 
   // Real fields [nf][n^3] (dtype) -> compact spectra D F[f] at dst.
@@ -325,7 +380,7 @@ struct Engine {
     r.real_in = real;
     r.real_dtype = dtype == MHD_FP64 ? 0 : 1;
     r.nf = nf;
-    for (int f = 0; f < nf; ++f) r.out[f] = iy(f);
+    set_out(r, 0);
     k.row(RM_XFWD_REAL, r, row_grid(), c->stream);
     T* yi[kMaxOut];
     T* yo[kMaxOut];
@@ -356,7 +411,7 @@ struct Engine {
     r.real_out = real;
     r.real_dtype = dtype == MHD_FP64 ? 0 : 1;
     r.nf = nf;
-    for (int f = 0; f < nf; ++f) r.in[f] = iy(f);
+    set_in(r, 0);
     k.row(RM_XINV_REAL, r, row_grid(), c->stream);
   }
 
@@ -370,19 +425,19 @@ struct Engine {
       zo[f] = iz(f);
       sp[f] = copy_spec(f, inv_n3());
     }
-    col(PK_ZINV, 4, zi, 4, zo, sp);
+    timed(MHD_PASS_ZINV_A, [&] { col(PK_ZINV, 4, zi, 4, zo, sp); });
     T* yo[4] = {iy(0), iy(1), iy(2), iy(3)};
-    y_copy(PK_YINV, 4, zo, yo);
+    timed(MHD_PASS_YINV_A, [&] { y_copy(PK_YINV, 4, zo, yo); });
     RowArgs<T> r = row_args();
-    for (int f = 0; f < 4; ++f) r.in[f] = iy(f);
-    for (int f = 0; f < 3; ++f) r.out[f] = iy(4 + f);
-    k.row(RM_XA, r, row_grid(), c->stream);
+    set_in(r, 0);
+    set_out(r, 4);
+    timed(MHD_PASS_XA, [&] { k.row(RM_XA, r, row_grid(), c->stream); });
     T* ui[3] = {iy(4), iy(5), iy(6)};
     T* uo[3] = {iz(0), iz(1), iz(2)};
-    y_copy(PK_YFWD, 3, ui, uo);
+    timed(MHD_PASS_YFWD_A, [&] { y_copy(PK_YFWD, 3, ui, uo); });
     T* ho[3] = {spec_field(uhat(), 0), spec_field(uhat(), 1), spec_field(uhat(), 2)};
     OutSpec cp[3] = {copy_spec(0, 1.0), copy_spec(1, 1.0), copy_spec(2, 1.0)};
-    col(PK_ZFWD, 3, uo, 3, ho, cp);
+    timed(MHD_PASS_ZFWD_A, [&] { col(PK_ZFWD, 3, uo, 3, ho, cp); });
   }
 
   // Phase B: fluxes and the spectral RHS of state U.  rout == nullptr: AB2
@@ -409,24 +464,26 @@ struct Engine {
     };
     T* zo[12];
     for (int f = 0; f < 12; ++f) zo[f] = iz(f);
-    col(PK_ZINV, 12, zi, 7, zo, sp);
+    timed(MHD_PASS_ZINV_B, [&] { col(PK_ZINV, 12, zi, 7, zo, sp); });
     T* yo[12];
     for (int f = 0; f < 12; ++f) yo[f] = iy(4 + f);
-    y_copy(PK_YINV, 12, zo, yo);
+    timed(MHD_PASS_YINV_B, [&] { y_copy(PK_YINV, 12, zo, yo); });
     RowArgs<T> r = row_args();
-    for (int f = 0; f < 16; ++f) r.in[f] = iy(f);
-    for (int f = 0; f < 12; ++f) r.out[f] = iy(f);
+    set_in(r, 0);
+    set_out(r, 0);
     r.partials = part();
-    k.row(RM_XB, r, row_grid(), c->stream);
+    timed(MHD_PASS_XB, [&] { k.row(RM_XB, r, row_grid(), c->stream); });
     if (!rout) {
       // per-step CFL speed and non-finite count, merged into the status words
-      hipLaunchKernelGGL(k_reduce, dim3(2), dim3(kThreads), 0, c->stream, part(), (int64_t)g.n * g.n / 2, 2,
-                         1u | 2u, 1, status());
+      timed(MHD_PASS_REDUCE, [&] {
+        hipLaunchKernelGGL(k_reduce, dim3(2), dim3(kThreads), 0, c->stream, part(), (int64_t)g.n * g.n / 2, 2,
+                           1u | 2u, 1, status());
+      });
     }
     T* fi[12];
     T* fo[12];
     for (int f = 0; f < 12; ++f) { fi[f] = iy(f); fo[f] = iz(f); }
-    y_copy(PK_YFWD, 12, fi, fo);
+    timed(MHD_PASS_YFWD_B, [&] { y_copy(PK_YFWD, 12, fi, fo); });
     RhsArgs<T> q;
     std::memset(&q, 0, sizeof(q));
     for (int f = 0; f < 12; ++f) q.flux[f] = iz(f);
@@ -454,7 +511,13 @@ struct Engine {
     q.a_prev = a_prev;
     q.eta = c->p.eta;
     q.g = g;
-    k.rhs(q, dim3(ztiles(), 8), c->stream);
+    timed(MHD_PASS_ZRHS, [&] { k.rhs(q, dim3((unsigned)(ztiles() * 8)), c->stream); });
+  }
+
+  double step_bytes() const {
+    double b = 0.0;
+    for (int cls = 0; cls < MHD_PASS_COUNT; ++cls) b += class_bytes(cls);
+    return b;
   }
 
   void reset_status() {
@@ -481,7 +544,7 @@ struct Engine {
     for (int f = 0; f < 12; ++f) yo[f] = iy(f);
     y_copy(PK_YINV, 12, zo, yo);
     RowArgs<T> r = row_args();
-    for (int f = 0; f < 12; ++f) r.in[f] = iy(f);
+    set_in(r, 0);
     r.partials = part();
     k.row(RM_XDIAG, r, row_grid(), c->stream);
     const unsigned maxmask = (1u << DQ_DIVB_MAX) | (1u << DQ_CFL_MAX);
@@ -725,7 +788,61 @@ int mhd_fft3d(mhd_ctx* c, int32_t dir, const void* d_in, void* d_out) {
   });
 }
 
+int mhd_profile(mhd_ctx* c, int32_t enable) {
+  if (!c) return MHD_E_ARG;
+  if (enable) {
+    constexpr int kCap = 4096;
+    if (c->ev.empty()) {
+      c->ev.resize(2 * kCap);
+      for (auto& e : c->ev) {
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess) return hip_fail(c, err, "mhd_profile");
+      }
+      c->rec_cls.assign(kCap, 0);
+      c->rec_bytes.assign(kCap, 0.0);
+    }
+    c->nrec = 0;
+    c->dropped = 0;
+  }
+  c->prof_on = enable != 0;
+  return MHD_OK;
+}
+
+int mhd_profile_read(mhd_ctx* c, double* ms, int64_t* launches, double* bytes, int64_t* dropped) {
+  if (!c) return MHD_E_ARG;
+  hipError_t err = hipStreamSynchronize(c->stream);
+  if (err != hipSuccess) return hip_fail(c, err, "mhd_profile_read");
+  double m[MHD_PASS_COUNT] = {0}, b[MHD_PASS_COUNT] = {0};
+  int64_t l[MHD_PASS_COUNT] = {0};
+  for (int r = 0; r < c->nrec; ++r) {
+    float e = 0.f;
+    err = hipEventElapsedTime(&e, c->ev[2 * r], c->ev[2 * r + 1]);
+    if (err != hipSuccess) return hip_fail(c, err, "mhd_profile_read elapsed");
+    const int cls = c->rec_cls[r];
+    m[cls] += e;
+    b[cls] += c->rec_bytes[r];
+    l[cls] += 1;
+  }
+  for (int i = 0; i < MHD_PASS_COUNT; ++i) {
+    if (ms) ms[i] = m[i];
+    if (launches) launches[i] = l[i];
+    if (bytes) bytes[i] = b[i];
+  }
+  if (dropped) *dropped = c->dropped;
+  return MHD_OK;
+}
+
+double mhd_step_bytes(const mhd_ctx* cc) {
+  if (!cc) return 0.0;
+  mhd_ctx* c = const_cast<mhd_ctx*>(cc);
+  double b = 0.0;
+  with_engine(c, [&](auto& e) { b = e.step_bytes(); return MHD_OK; });
+  return b;
+}
+
 int mhd_destroy(mhd_ctx* c) {
+  if (!c) return MHD_OK;
+  for (auto& e : c->ev) hipEventDestroy(e);
   delete c;
   return MHD_OK;
 }

@@ -86,8 +86,10 @@ enum RowMode { RM_XA = 0, RM_XB = 1, RM_XFWD_REAL = 2, RM_XINV_REAL = 3, RM_XDIA
 
 template <typename T>
 struct RowArgs {
-  const T* in[kRowFields];  // I_y slot bases (complex)
-  T* out[kRowFields];
+  const T* in0;             // first input I_y slot (complex); field f at in0 + 2 f in_stride
+  int64_t in_stride;        // complex values between consecutive input fields
+  T* out0;                  // first output I_y slot
+  int64_t out_stride;
   const void* real_in;      // [nf][n^3] real rows (RM_XFWD_REAL)
   void* real_out;           // [nf][n^3] real rows (RM_XINV_REAL)
   int32_t real_dtype;       // 0 = double, 1 = float

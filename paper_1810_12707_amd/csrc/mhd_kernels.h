@@ -26,11 +26,11 @@ template <int N> struct Band {
 template <int N> __device__ __forceinline__ int band_pos(int l) { return l <= Band<N>::K ? l : l + N - Band<N>::NB; }
 template <int N> __device__ __forceinline__ int band_k(int l) { return l <= Band<N>::K ? l : l - Band<N>::NB; }
 
-// Column tile width: keeps the LDS tile at <= 64 KiB.
+// Column tile width: 16 columns while the LDS tile stays within 32 KiB (four
+// workgroups per CU), else 8.
 template <typename T, int N> constexpr int col_width() {
   constexpr int bytes = N * 2 * (int)sizeof(T);
-  constexpr int c = 65536 / bytes;
-  return c >= 16 ? 16 : (c >= 8 ? 8 : 4);
+  return 32768 / bytes >= 16 ? 16 : 8;
 }
 
 template <typename T>
@@ -68,22 +68,44 @@ __device__ __forceinline__ void load_twiddles(cx<T>* stw, const T* tw, int tid) 
   for (int i = tid; i < N; i += kThreads) stw[i] = ld(tw, i);
 }
 
+// Band index of position q on a length-N axis, or -1 in the dropped gap.
+template <int N> __device__ __forceinline__ int pos_band(int q) {
+  return q <= Band<N>::K ? q : (q >= N - Band<N>::K ? q - N + Band<N>::NB : -1);
+}
+
+// Decode a flat workgroup id into (tile, field) with the field fastest, after
+// the XCD remap: the outputs of one column tile run back to back on one XCD and
+// share the L2 copies of the inputs they have in common.
+struct TileField {
+  int tile, field;
+};
+__device__ __forceinline__ TileField tile_field(int nfields) {
+  const int L = xcd_remap(blockIdx.x, gridDim.x);
+  TileField t;
+  t.tile = L / nfields;
+  t.field = L - t.tile * nfields;
+  return t;
+}
+
 // ------------------------------------------------------------------ k_col
 // S = +1: inverse pass, band (nb) in -> N out.  S = -1: forward, N in -> band out.
-// blockIdx.x = outer * ntiles + tile, blockIdx.y = output field.
+// Flat grid over (outer, tile, field); see tile_field.  The first FFT pass
+// loads straight from global memory (skipping the zero gap of a band input);
+// the last pass stores straight to global memory (skipping dropped modes).
 template <typename T, int N, int S>
 __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   constexpr int C = col_width<T, N>();
-  constexpr int K = Band<N>::K, NH = Band<N>::NH, NBB = Band<N>::NB;
+  constexpr int NH = Band<N>::NH, NBB = Band<N>::NB;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
-  const int f = blockIdx.y;
+  const TileField tf = tile_field(a.nout);
+  const int f = tf.field;
   const bool zpass = (a.kind == PK_ZINV || a.kind == PK_ZFWD);
   const int ncols = zpass ? NBB * NH : NH;
   const int ntiles = (ncols + C - 1) / C;
-  const int outer = blockIdx.x / ntiles;
-  const int c0 = (blockIdx.x - outer * ntiles) * C;
+  const int outer = tf.tile / ntiles;
+  const int c0 = (tf.tile - outer * ntiles) * C;
   // strides (complex elements) of the input and output layouts
   int64_t os_in, ls_in, os_out, ls_out;
   switch (a.kind) {
@@ -94,147 +116,194 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   }
   load_twiddles<T, N>(stw, a.tw, tid);
   const OutSpec& sp = a.spec[f];
-  constexpr int LIN = (S > 0) ? NBB : N;
-  for (int e = tid; e < LIN * C; e += kThreads) {
-    const int l = e / C, c = e - (e / C) * C;
+  const int nt = sp.nterms;
+  const T* p0 = a.in[sp.t[0].src];
+  const T* p1 = nt > 1 ? a.in[sp.t[1].src] : p0;
+  const T* p2 = nt > 2 ? a.in[sp.t[2].src] : p0;
+  const T* const* in = a.in;
+  (void)in;
+  const int64_t base_in = outer * os_in + c0;
+  auto load = [&](int c, int q) -> cx<T> {
     const int col = c0 + c;
     cx<T> v = mk<T>(0, 0);
-    if (col < ncols) {
-      int kx = 0, ky = 0, kz = 0;
-      if (zpass) {
-        ky = band_k<N>(col / NH);
-        kx = col - (col / NH) * NH;
-        if (S > 0) kz = band_k<N>(l);
-      } else {
-        kx = col;
-        if (S > 0) ky = band_k<N>(l);
+    if (col >= ncols) return v;
+    int l = q;
+    if constexpr (S > 0) {
+      l = pos_band<N>(q);
+      if (l < 0) return v;
+    }
+    const int64_t idx = base_in + l * ls_in + c;
+    int kx, ky = 0, kz = 0;
+    if (zpass) {
+      ky = band_k<N>(col / NH);
+      kx = col - (col / NH) * NH;
+      if (S > 0) kz = band_k<N>(l);
+    } else {
+      kx = col;
+      if (S > 0) ky = band_k<N>(l);
+    }
+    const cx<T> x0 = ld(p0, idx);
+    const cx<T> x1 = nt > 1 ? ld(p1, idx) : mk<T>(0, 0);
+    const cx<T> x2 = nt > 2 ? ld(p2, idx) : mk<T>(0, 0);
+    const cx<T> xs[3] = {x0, x1, x2};
+#pragma unroll
+    for (int t = 0; t < kMaxTerms; ++t) {
+      if (t < nt) {
+        const Term& tm = sp.t[t];
+        const T cf = T(tm.coef);
+        const cx<T> xv = xs[t];
+        if (tm.axis < 0) {
+          v.x += cf * xv.x;
+          v.y += cf * xv.y;
+        } else {
+          const T ck = cf * T(tm.axis == 0 ? kx : (tm.axis == 1 ? ky : kz));
+          v.x -= ck * xv.y;
+          v.y += ck * xv.x;
+        }
       }
-      v = combine<T>(sp, a.in, outer * os_in + l * ls_in + col, kx, ky, kz);
     }
-    const int pos = (S > 0) ? band_pos<N>(l) : l;
-    tile[pos * C + c] = v;
-  }
-  if constexpr (S > 0) {
-    for (int e = tid; e < (N - NBB) * C; e += kThreads) tile[(K + 1) * C + e] = mk<T>(0, 0);
-  }
-  __syncthreads();
-  lds_fft<T, N, C, kThreads, C, 1, S>(tile, stw, tid, C);
-  constexpr int LOUT = (S > 0) ? N : NBB;
+    return v;
+  };
   T* out = a.out[f];
-  for (int e = tid; e < LOUT * C; e += kThreads) {
-    const int l = e / C, c = e - (e / C) * C;
-    const int col = c0 + c;
-    if (col < ncols) {
-      const int pos = (S > 0) ? l : band_pos<N>(l);
-      st(out, outer * os_out + l * ls_out + col, tile[pos * C + c]);
+  const int64_t base_out = outer * os_out + c0;
+  auto store = [&](int, int, int c, int q, cx<T> v) {
+    if (c0 + c >= ncols) return;
+    int l = q;
+    if constexpr (S < 0) {
+      l = pos_band<N>(q);
+      if (l < 0) return;
     }
-  }
+    st(out, base_out + l * ls_out + c, v);
+  };
+  fft_reg<T, N, C, kThreads, C, 1, S>(tile, stw, tid, C, load, store);
 }
 
 // ------------------------------------------------------------------ k_zfwd_rhs
-// blockIdx.x = column tile of (ky, kx), blockIdx.y = output field f (0..7).
+// Flat grid over (column tile of (ky, kx), output field f = 0..7), field fastest.
 template <typename T, int N>
 __global__ void __launch_bounds__(kThreads) k_zfwd_rhs(const RhsArgs<T> a) {
   constexpr int C = col_width<T, N>();
   constexpr int NH = Band<N>::NH, NBB = Band<N>::NB;
   constexpr int NCOLS = NBB * NH;
-  constexpr int CNT = (NBB * C + kThreads - 1) / kThreads;
+  using LP = LastPass<N, C, kThreads>;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
-  const int f = blockIdx.y;
-  const int c0 = blockIdx.x * C;
+  const TileField tf = tile_field(8);
+  const int f = tf.field;
+  const int c0 = tf.tile * C;
   const int64_t sc = a.g.sc;
   const int64_t LS = NCOLS;  // row stride of I_z (z) and of compact (kz)
-  cx<T> acc[CNT];
-#pragma unroll
-  for (int i = 0; i < CNT; ++i) acc[i] = mk<T>(0, 0);
+  const T dt = T(a.dt), ac = T(a.a_cur), ap = T(a.a_prev);
+  const bool use_prev = a.a_prev != 0.0;
+
+  // R_f -> store, or the AB2 update U += dt (a_cur R^n + a_prev R^{n-1}), R^{n-1} <- R^n
+  auto finish = [&](int64_t idx, cx<T> R) {
+    if (a.rout) {
+      st(a.rout, idx, R);
+    } else {
+      cx<T> u = ld(a.state, idx);
+      cx<T> inc = cscale(R, ac);
+      if (use_prev) inc = cadd(inc, cscale(ld(a.rprev, idx), ap));
+      u.x += dt * inc.x;
+      u.y += dt * inc.y;
+      st(a.state, idx, u);
+      st(a.rprev, idx, R);
+    }
+  };
 
   if (f == 0) {
     // MHD1: R_rho = -i k . m^ (state fields 1..3, already band-limited)
-#pragma unroll
-    for (int i = 0; i < CNT; ++i) {
-      const int e = tid + i * kThreads;
+    for (int e = tid; e < NBB * C; e += kThreads) {
       const int l = e / C, c = e - (e / C) * C, col = c0 + c;
-      if (l < NBB && col < NCOLS) {
+      if (col < NCOLS) {
         const int kz = band_k<N>(l), ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
         const int64_t idx = (int64_t)l * LS + col;
         const cx<T> mx = ld(a.state, 1 * sc + idx), my = ld(a.state, 2 * sc + idx), mz = ld(a.state, 3 * sc + idx);
         const T dx = T(kx) * mx.x + T(ky) * my.x + T(kz) * mz.x;
         const T dy = T(kx) * mx.y + T(ky) * my.y + T(kz) * mz.y;
-        acc[i] = mk<T>(dy, -dx);  // -i (dx + i dy)
+        finish(idx, mk<T>(dy, -dx));  // -i (dx + i dy)
       }
     }
-  } else {
-    load_twiddles<T, N>(stw, a.tw, tid);
-    for (int grp = 0; grp < 2; ++grp) {
-      const OutSpec& sp = grp == 0 ? a.A[f] : a.Z[f];
-      if (sp.nterms == 0) continue;  // uniform across the block
-      if (grp == 1) __syncthreads();  // the tile is about to be overwritten
-      for (int e = tid; e < N * C; e += kThreads) {
-        const int l = e / C, c = e - (e / C) * C, col = c0 + c;
-        cx<T> v = mk<T>(0, 0);
-        if (col < NCOLS) {
-          const int ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
-          v = combine<T>(sp, a.flux, (int64_t)l * LS + col, kx, ky, 0);
-        }
-        tile[l * C + c] = v;
-      }
-      __syncthreads();
-      lds_fft<T, N, C, kThreads, C, 1, -1>(tile, stw, tid, C);
+    return;
+  }
+  load_twiddles<T, N>(stw, a.tw, tid);
+  cx<T> acc[LP::CNT][LP::R];
 #pragma unroll
-      for (int i = 0; i < CNT; ++i) {
-        const int e = tid + i * kThreads;
-        const int l = e / C, c = e - (e / C) * C;
-        if (l < NBB) {
-          const cx<T> v = tile[band_pos<N>(l) * C + c];
-          if (grp == 0) {
-            acc[i] = cadd(acc[i], v);
-          } else {  // + i kz * v
-            const T kz = T(band_k<N>(l));
-            acc[i].x -= kz * v.y;
-            acc[i].y += kz * v.x;
+  for (int i = 0; i < LP::CNT; ++i)
+#pragma unroll
+    for (int r = 0; r < LP::R; ++r) acc[i][r] = mk<T>(0, 0);
+
+  for (int grp = 0; grp < 2; ++grp) {
+    const OutSpec& sp = grp == 0 ? a.A[f] : a.Z[f];
+    const int nt = sp.nterms;
+    if (nt == 0) continue;           // uniform across the block
+    if (grp == 1) __syncthreads();   // the LDS tile is about to be rewritten
+    const T* p0 = a.flux[sp.t[0].src];
+    const T* p1 = nt > 1 ? a.flux[sp.t[1].src] : p0;
+    auto load = [&](int c, int q) -> cx<T> {
+      const int col = c0 + c;
+      cx<T> v = mk<T>(0, 0);
+      if (col >= NCOLS) return v;
+      const int ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+      const int64_t idx = (int64_t)q * LS + col;
+      const cx<T> x0 = ld(p0, idx);
+      const cx<T> x1 = nt > 1 ? ld(p1, idx) : mk<T>(0, 0);
+      const cx<T> xs[2] = {x0, x1};
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        if (t < nt) {
+          const Term& tm = sp.t[t];
+          const T cf = T(tm.coef);
+          if (tm.axis < 0) {
+            v.x += cf * xs[t].x;
+            v.y += cf * xs[t].y;
+          } else {
+            const T ck = cf * T(tm.axis == 0 ? kx : ky);
+            v.x -= ck * xs[t].y;
+            v.y += ck * xs[t].x;
           }
         }
       }
-    }
-    if (f >= 4 && f <= 6) {
-      // MHD4 resistive term: - eta |k|^2 B^
-      const T eta = T(a.eta);
-#pragma unroll
-      for (int i = 0; i < CNT; ++i) {
-        const int e = tid + i * kThreads;
-        const int l = e / C, c = e - (e / C) * C, col = c0 + c;
-        if (l < NBB && col < NCOLS) {
-          const int kz = band_k<N>(l), ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
-          const T k2 = T(kx * kx + ky * ky + kz * kz);
-          const cx<T> b = ld(a.state, f * sc + (int64_t)l * LS + col);
-          acc[i].x -= eta * k2 * b.x;
-          acc[i].y -= eta * k2 * b.y;
-        }
+      return v;
+    };
+    auto store = [&](int i, int r, int, int q, cx<T> v) {
+      if (grp == 0) {
+        acc[i][r] = cadd(acc[i][r], v);
+      } else {  // + i kz v
+        const int l = pos_band<N>(q);
+        const T kz = T(l < 0 ? 0 : band_k<N>(l));
+        acc[i][r].x -= kz * v.y;
+        acc[i][r].y += kz * v.x;
       }
-    }
+    };
+    fft_reg<T, N, C, kThreads, C, 1, -1>(tile, stw, tid, C, load, store);
   }
-  // store R, or the AB2 update U += dt (a_cur R^n + a_prev R^{n-1}); R^{n-1} <- R^n
-  const T dt = T(a.dt), ac = T(a.a_cur), ap = T(a.a_prev);
-  const bool use_prev = a.a_prev != 0.0;
+  // epilogue over this thread's last-pass positions: resistive term, update
+  const T eta = T(a.eta);
 #pragma unroll
-  for (int i = 0; i < CNT; ++i) {
-    const int e = tid + i * kThreads;
-    const int l = e / C, c = e - (e / C) * C, col = c0 + c;
-    if (l < NBB && col < NCOLS) {
+  for (int i = 0; i < LP::CNT; ++i) {
+    const int w = tid + i * kThreads;
+    const int c = w % C, j = w / C;
+    if (LP::TOT % kThreads != 0 && w >= LP::TOT) continue;
+    const int col = c0 + c;
+    if (col >= NCOLS) continue;
+    const int ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+#pragma unroll
+    for (int r = 0; r < LP::R; ++r) {
+      const int l = pos_band<N>(j + r * LP::NBF);
+      if (l < 0) continue;
       const int64_t idx = f * sc + (int64_t)l * LS + col;
-      if (a.rout) {
-        st(a.rout, idx, acc[i]);
-      } else {
-        cx<T> u = ld(a.state, idx);
-        cx<T> inc = cscale(acc[i], ac);
-        if (use_prev) inc = cadd(inc, cscale(ld(a.rprev, idx), ap));
-        u.x += dt * inc.x;
-        u.y += dt * inc.y;
-        st(a.state, idx, u);
-        st(a.rprev, idx, acc[i]);
+      cx<T> R = acc[i][r];
+      if (f >= 4 && f <= 6) {
+        // MHD4 resistive term: - eta |k|^2 B^
+        const int kz = band_k<N>(l);
+        const T k2 = T(kx * kx + ky * ky + kz * kz);
+        const cx<T> b = ld(a.state, idx);
+        R.x -= eta * k2 * b.x;
+        R.y -= eta * k2 * b.y;
       }
+      finish(idx, R);
     }
   }
 }
@@ -302,23 +371,25 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
     }
     __syncthreads();
   } else {
-    // Hermitian half rows (kx = 0..K) of two rows -> packed full spectrum
-    // Z[k] = X0[k] + i X1[k], Z[N-k] = conj(X0[k]) + i conj(X1[k]).
-    for (int e = tid; e < nin * N; e += kThreads) {
-      const int fld = e / N, q = e - (e / N) * N;
-      cx<T> z = mk<T>(0, 0);
-      if (q <= K || q >= N - K) {
-        const int k = q <= K ? q : N - q;
-        const cx<T> x0 = ld(a.in[fld], row0 * NH + k);
-        const cx<T> x1 = ld(a.in[fld], (row0 + 1) * NH + k);
-        if (q == 0) z = mk<T>(x0.x, x1.x);
-        else if (q <= K) z = mk<T>(x0.x - x1.y, x0.y + x1.x);
-        else z = mk<T>(x0.x + x1.y, x1.x - x0.y);
-      }
-      buf[fld * BS + q] = z;
-    }
+    // Inverse x transform.  The first FFT pass reads the Hermitian half rows
+    // (kx = 0..K) of both rows straight from global memory as the packed
+    // spectrum Z[q] = X0[q] + i X1[q] (q <= K), Z[N-k] = conj(X0[k]) + i conj(X1[k]);
+    // the last pass leaves the packed real rows (row0 + i row1) in LDS.
+    const T* in0 = a.in0;
+    const int64_t ist = a.in_stride;
+    auto load = [&](int fld, int q) -> cx<T> {
+      if (q > K && q < N - K) return mk<T>(0, 0);
+      const int k = q <= K ? q : N - q;
+      const T* src = in0 + 2 * fld * ist;
+      const cx<T> x0 = ld(src, row0 * NH + k);
+      const cx<T> x1 = ld(src, (row0 + 1) * NH + k);
+      if (q == 0) return mk<T>(x0.x, x1.x);
+      if (q <= K) return mk<T>(x0.x - x1.y, x0.y + x1.x);
+      return mk<T>(x0.x + x1.y, x1.x - x0.y);
+    };
+    auto store = [&](int, int, int fld, int q, cx<T> v) { buf[fld * BS + q] = v; };
+    fft_reg<T, N, NB, kThreads, 1, BS, +1, 1>(buf, stw, tid, nin, load, store);
     __syncthreads();
-    lds_fft<T, N, NB, kThreads, 1, BS, +1>(buf, stw, tid, nin);
   }
 
   if constexpr (MODE == RM_XINV_REAL) {
@@ -348,7 +419,6 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
         buf[i * BS + x] = mk<T>(m.x * i0, m.y * i1);
       }
     }
-    __syncthreads();
   }
 
   if constexpr (MODE == RM_XB) {
@@ -357,7 +427,8 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
     // 12 S_yz, 13-15 J.  Outputs: 0 Pi_xx, 1 Pi_yy, 2 Pi_zz, 3 Pi_xy,
     // 4 Pi_xz, 5 Pi_yz, 6-8 F^E, 9-11 e = u x B.
     const T gm1 = T(a.gamma - 1.0), gam = T(a.gamma), two_nu = T(2.0 * a.nu), eta = T(a.eta);
-    double cfl = 0.0, bad = 0.0;
+    T cfl = T(0);
+    int bad = 0;
     for (int x = tid; x < N; x += kThreads) {
       cx<T> v[16];
 #pragma unroll
@@ -400,20 +471,21 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
           if (h == 0) o[q].x = out[q];
           else o[q].y = out[q];
         }
+        // fastest signal speed for the CFL limit, and a non-finite check
         const T umax = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
-        const double c = double(umax) + sqrt(double(gam * P + B2) / double(rho));
+        const T c = umax + sqrt((gam * P + B2) * ir);
         if (!(c <= cfl)) cfl = c;  // NaN propagates
-        bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) && finite_(By) &&
-                   finite_(Bz) && finite_(E);
-        bad += fin ? 0.0 : 1.0;
+        const bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) &&
+                         finite_(By) && finite_(Bz) && finite_(E);
+        bad += fin ? 0 : 1;
       }
 #pragma unroll
       for (int q = 0; q < 12; ++q) buf[q * BS + x] = o[q];
     }
     // per-block CFL max and non-finite count (deterministic tree reduction)
     __shared__ double s_red[kThreads];
-    const double cfl_b = block_reduce(cfl, true, s_red, tid);
-    const double bad_b = block_reduce(bad, false, s_red, tid);
+    const double cfl_b = block_reduce(double(cfl), true, s_red, tid);
+    const double bad_b = block_reduce(double(bad), false, s_red, tid);
     if (tid == 0) {
       a.partials[2 * (int64_t)p + 0] = cfl_b;
       a.partials[2 * (int64_t)p + 1] = bad_b;
@@ -467,16 +539,19 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
 
   if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
     __syncthreads();
-    lds_fft<T, N, NB, kThreads, 1, BS, -1>(buf, stw, tid, nout);
+    lds_fft<T, N, NB, kThreads, 1, BS, -1, 1>(buf, stw, tid, nout);
     // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
+    T* out0 = a.out0;
+    const int64_t ost = a.out_stride;
     for (int e = tid; e < nout * NH; e += kThreads) {
       const int fld = e / NH, k = e - (e / NH) * NH;
       const cx<T> zk = buf[fld * BS + k];
       const cx<T> zm = buf[fld * BS + (k == 0 ? 0 : N - k)];
       const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
       const cx<T> x1 = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
-      st(a.out[fld], row0 * NH + k, x0);
-      st(a.out[fld], (row0 + 1) * NH + k, x1);
+      T* dst = out0 + 2 * fld * ost;
+      st(dst, row0 * NH + k, x0);
+      st(dst, (row0 + 1) * NH + k, x1);
     }
   }
 }

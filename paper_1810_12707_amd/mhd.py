@@ -25,8 +25,10 @@ MHD_FLAG_CHECK_CFL = 1
 EXPORTED = (
     "mhd_supported_size", "mhd_workspace_bytes", "mhd_init", "mhd_set_state", "mhd_get_state",
     "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_destroy",
-    "mhd_status_string", "mhd_last_error",
+    "mhd_status_string", "mhd_last_error", "mhd_profile", "mhd_profile_read", "mhd_step_bytes",
 )
+
+PASS_NAMES = ("zinv_a", "yinv_a", "xa", "yfwd_a", "zfwd_a", "zinv_b", "yinv_b", "xb", "yfwd_b", "zrhs", "reduce")
 
 
 class mhd_params(ctypes.Structure):
@@ -91,6 +93,13 @@ def lib() -> ctypes.CDLL:
         L.mhd_status_string.restype = ctypes.c_char_p
         L.mhd_last_error.argtypes = [vp]
         L.mhd_last_error.restype = ctypes.c_char_p
+        L.mhd_profile.argtypes = [vp, ctypes.c_int32]
+        L.mhd_profile.restype = ctypes.c_int
+        dp, lp = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+        L.mhd_profile_read.argtypes = [vp, dp, lp, dp, lp]
+        L.mhd_profile_read.restype = ctypes.c_int
+        L.mhd_step_bytes.argtypes = [vp]
+        L.mhd_step_bytes.restype = ctypes.c_double
         for name in ("mhd_supported_size", "mhd_init", "mhd_set_state", "mhd_get_state", "mhd_rhs",
                      "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -186,6 +195,23 @@ def mhd_fft3d(ctx, direction: int, x_in, x_out):
         "mhd_fft3d", ctx)
 
 
+def mhd_profile(ctx, enable: bool):
+    _rc(lib().mhd_profile(ctx, 1 if enable else 0), "mhd_profile", ctx)
+
+
+def mhd_profile_read(ctx) -> dict:
+    k = len(PASS_NAMES)
+    ms, nl, by, dr = (ctypes.c_double * k)(), (ctypes.c_int64 * k)(), (ctypes.c_double * k)(), ctypes.c_int64()
+    _rc(lib().mhd_profile_read(ctx, ms, nl, by, ctypes.byref(dr)), "mhd_profile_read", ctx)
+    out = {name: {"ms": ms[i], "launches": nl[i], "bytes": by[i]} for i, name in enumerate(PASS_NAMES)}
+    out["dropped"] = dr.value
+    return out
+
+
+def mhd_step_bytes(ctx) -> float:
+    return float(lib().mhd_step_bytes(ctx))
+
+
 def mhd_destroy(ctx):
     lib().mhd_destroy(ctx)
 
@@ -253,6 +279,16 @@ class Solver:
         out = self.torch.empty((n, n, n), dtype=self.real_dtype, device=self.device)
         mhd_fft3d(self.ctx, 1, spec, out)
         return out
+
+    def profile(self, enable=True):
+        mhd_profile(self.ctx, enable)
+
+    def profile_read(self) -> dict:
+        return mhd_profile_read(self.ctx)
+
+    @property
+    def step_bytes(self) -> float:
+        return mhd_step_bytes(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
