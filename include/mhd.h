@@ -21,8 +21,10 @@
  *  - A mode is retained iff 3|k| < n on all three axes; K = (n-1)/3 is the
  *    largest retained |k| per axis.
  *  - Compact spectra (the state and the mhd_fft3d hook) are complex arrays
- *    [kz][ky][kx] of (2K+1) x (2K+1) x (K+1) interleaved (re, im) pairs in the
- *    working precision; kz and ky run 0..K then -K..-1, kx runs 0..K.
+ *    [kz][ky][kx] of (2K+1) x (2K+1) x P interleaved (re, im) pairs in the
+ *    working precision, P = mhd_spectrum_pitch(n) = K+1 rounded up to a
+ *    multiple of 8; kz and ky run 0..K then -K..-1, kx runs 0..K, and the
+ *    entries kx = K+1..P-1 are padding that is neither read nor written.
  *  - Every call enqueues work on the stream given to mhd_init and returns
  *    without waiting, except where a function says it synchronises.
  *  - All device memory belongs to the caller: the workspace passed to
@@ -149,8 +151,11 @@ int mhd_diagnostics(mhd_ctx* ctx, mhd_diag* h_out);
  * precision; the arrays may not overlap.  Uses the context's workspace. */
 int mhd_fft3d(mhd_ctx* ctx, int32_t dir, const void* d_in, void* d_out);
 
-/* Number of complex values of one compact spectrum, (2K+1)^2 (K+1). */
+/* Number of complex values of one compact spectrum, (2K+1)^2 P. */
 int64_t mhd_spectrum_size(int32_t n);
+
+/* kx pitch P of the compact spectrum (K+1 rounded up to a multiple of 8). */
+int32_t mhd_spectrum_pitch(int32_t n);
 
 /* Launch classes of one step, for mhd_profile_read.  Suffix _A: phase A
  * (u^ = D F[m/rho]); _B: phase B (fluxes and update). */

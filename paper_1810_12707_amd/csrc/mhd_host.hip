@@ -95,11 +95,11 @@ k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restr
   const int tid = threadIdx.x;
   const int64_t idx = (int64_t)blockIdx.x * kThreads + tid;
   double q[kSpecQ] = {0.0, 0.0, 0.0};
-  if (idx < g.sc) {
-    const int64_t plane = (int64_t)g.nb * g.nh;
-    const int lz = (int)(idx / plane);
-    const int rem = (int)(idx - (int64_t)lz * plane);
-    const int ly = rem / g.nh, kx = rem - ly * g.nh;
+  const int64_t plane = (int64_t)g.nb * g.nhp;
+  const int lz = (int)(idx / plane);
+  const int rem = (int)(idx - (int64_t)lz * plane);
+  const int ly = rem / g.nhp, kx = rem - ly * g.nhp;
+  if (idx < g.sc && kx < g.nh) {  // padding columns hold no data and are not read
     const int kz = lz <= g.K ? lz : lz - g.nb;
     const int ky = ly <= g.K ? ly : ly - g.nb;
     const double w = kx == 0 ? 1.0 : 2.0;
@@ -165,9 +165,10 @@ Geo make_geo(int n) {
   g.K = (n - 1) / 3;
   g.nh = g.K + 1;
   g.nb = 2 * g.K + 1;
-  g.sc = (int64_t)g.nb * g.nb * g.nh;
-  g.iz = (int64_t)n * g.nb * g.nh;
-  g.iy = (int64_t)n * n * g.nh;
+  g.nhp = (g.nh + 7) / 8 * 8;
+  g.sc = (int64_t)g.nb * g.nb * g.nhp;
+  g.iz = (int64_t)n * g.nb * g.nhp;
+  g.iy = (int64_t)n * n * g.nhp;
   g.n3 = (int64_t)n * n * n;
   return g;
 }
@@ -278,9 +279,11 @@ struct Engine {
   double* status() const { return reinterpret_cast<double*>(c->ws + c->L.status); }
   double* res() const { return reinterpret_cast<double*>(c->ws + c->L.res); }
 
-  // Algorithmic HBM bytes of one launch: each array read or written once.
+  // Algorithmic HBM bytes of one launch: each array read or written once,
+  // counting data entries only (the kx padding is never touched).
   double cbytes(double n_sc, double n_iz, double n_iy) const {
-    return (n_sc * (double)g.sc + n_iz * (double)g.iz + n_iy * (double)g.iy) * 2.0 * sizeof(T);
+    const double nb = g.nb, nh = g.nh, n = g.n;
+    return (n_sc * nb * nb * nh + n_iz * n * nb * nh + n_iy * n * n * nh) * 2.0 * sizeof(T);
   }
   double class_bytes(int cls) const {
     switch (cls) {
@@ -315,7 +318,7 @@ struct Engine {
     }
   }
 
-  int ztiles() const { return (int)((g.nb * g.nh + k.col_width - 1) / k.col_width); }
+  int ztiles() const { return (int)(((int64_t)g.nb * g.nhp + k.col_width - 1) / k.col_width); }
   int ytiles() const { return (g.nh + k.col_width - 1) / k.col_width; }
 
   ColArgs<T> col_args(int kind, int nout) const {
@@ -601,6 +604,11 @@ int mhd_supported_size(int32_t n, int32_t precision) { return size_ok(n, precisi
 int64_t mhd_spectrum_size(int32_t n) {
   if (n < 1) return 0;
   return make_geo(n).sc;
+}
+
+int32_t mhd_spectrum_pitch(int32_t n) {
+  if (n < 1) return 0;
+  return make_geo(n).nhp;
 }
 
 size_t mhd_workspace_bytes(const mhd_params* p) {

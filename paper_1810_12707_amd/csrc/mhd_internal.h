@@ -1,10 +1,12 @@
 // Internal definitions shared by the HIP kernels and the host side of libmhd.
 //
 // Data layout in HBM (per field, working precision T, complex = interleaved
-// (re, im) pairs; K = (n-1)/3, nh = K+1, nb = 2K+1):
-//   compact spectrum S  [kz: nb][ky: nb][kx: nh]  (state, history, u^)
-//   z-pass intermediate [z: n][ky: nb][kx: nh]    ("I_z")
-//   y-pass intermediate [z: n][y: n][kx: nh]      ("I_y")
+// (re, im) pairs; K = (n-1)/3, nh = K+1, nb = 2K+1, nhp = nh rounded up to a
+// multiple of 8 so that every kx row starts on a 64-byte boundary):
+//   compact spectrum S  [kz: nb][ky: nb][kx: nhp]  (state, history, u^)
+//   z-pass intermediate [z: n][ky: nb][kx: nhp]    ("I_z")
+//   y-pass intermediate [z: n][y: n][kx: nhp]      ("I_y")
+// Entries with kx >= nh are padding: never read, never written.
 // Band indices run 0..K then -K..-1; along a length-n axis, band index l sits
 // at position l (l <= K) or l + n - nb (l > K).
 #pragma once
@@ -48,6 +50,7 @@ enum PassKind { PK_ZINV = 0, PK_YINV = 1, PK_YFWD = 2, PK_ZFWD = 3 };
 
 struct Geo {
   int32_t n, K, nh, nb;
+  int32_t nhp;  // kx pitch: nh rounded up to a multiple of 8
   int64_t sc;  // complex values per compact spectrum
   int64_t iz;  // complex values per I_z field
   int64_t iy;  // complex values per I_y field

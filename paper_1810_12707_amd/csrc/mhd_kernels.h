@@ -20,6 +20,7 @@ template <int N> struct Band {
   static constexpr int K = (N - 1) / 3;
   static constexpr int NH = K + 1;
   static constexpr int NB = 2 * K + 1;
+  static constexpr int NHP = (NH + 7) / 8 * 8;  // kx pitch of every layout (64-byte rows)
 };
 
 // Position of band index l on a length-N axis, and its wavenumber.
@@ -95,24 +96,26 @@ __device__ __forceinline__ TileField tile_field(int nfields) {
 template <typename T, int N, int S>
 __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   constexpr int C = col_width<T, N>();
-  constexpr int NH = Band<N>::NH, NBB = Band<N>::NB;
+  constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
   const TileField tf = tile_field(a.nout);
   const int f = tf.field;
   const bool zpass = (a.kind == PK_ZINV || a.kind == PK_ZFWD);
-  const int ncols = zpass ? NBB * NH : NH;
+  // z passes: columns are (ky, kx) flattened over the padded pitch; padding
+  // columns (kx >= NH) are never read or written
+  const int ncols = zpass ? NBB * NHP : NH;
   const int ntiles = (ncols + C - 1) / C;
   const int outer = tf.tile / ntiles;
   const int c0 = (tf.tile - outer * ntiles) * C;
   // strides (complex elements) of the input and output layouts
   int64_t os_in, ls_in, os_out, ls_out;
   switch (a.kind) {
-    case PK_ZINV: os_in = 0; ls_in = NBB * NH; os_out = 0; ls_out = NBB * NH; break;
-    case PK_YINV: os_in = (int64_t)NBB * NH; ls_in = NH; os_out = (int64_t)N * NH; ls_out = NH; break;
-    case PK_YFWD: os_in = (int64_t)N * NH; ls_in = NH; os_out = (int64_t)NBB * NH; ls_out = NH; break;
-    default: os_in = 0; ls_in = NBB * NH; os_out = 0; ls_out = NBB * NH; break;
+    case PK_ZINV: os_in = 0; ls_in = NBB * NHP; os_out = 0; ls_out = NBB * NHP; break;
+    case PK_YINV: os_in = (int64_t)NBB * NHP; ls_in = NHP; os_out = (int64_t)N * NHP; ls_out = NHP; break;
+    case PK_YFWD: os_in = (int64_t)N * NHP; ls_in = NHP; os_out = (int64_t)NBB * NHP; ls_out = NHP; break;
+    default: os_in = 0; ls_in = NBB * NHP; os_out = 0; ls_out = NBB * NHP; break;
   }
   load_twiddles<T, N>(stw, a.tw, tid);
   const OutSpec& sp = a.spec[f];
@@ -123,10 +126,13 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   const T* const* in = a.in;
   (void)in;
   const int64_t base_in = outer * os_in + c0;
+  auto col_ok = [&](int col) {
+    return col < ncols && (!zpass || col - (col / NHP) * NHP < NH);
+  };
   auto load = [&](int c, int q) -> cx<T> {
     const int col = c0 + c;
     cx<T> v = mk<T>(0, 0);
-    if (col >= ncols) return v;
+    if (!col_ok(col)) return v;
     int l = q;
     if constexpr (S > 0) {
       l = pos_band<N>(q);
@@ -135,8 +141,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
     const int64_t idx = base_in + l * ls_in + c;
     int kx, ky = 0, kz = 0;
     if (zpass) {
-      ky = band_k<N>(col / NH);
-      kx = col - (col / NH) * NH;
+      ky = band_k<N>(col / NHP);
+      kx = col - (col / NHP) * NHP;
       if (S > 0) kz = band_k<N>(l);
     } else {
       kx = col;
@@ -167,7 +173,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   T* out = a.out[f];
   const int64_t base_out = outer * os_out + c0;
   auto store = [&](int, int, int c, int q, cx<T> v) {
-    if (c0 + c >= ncols) return;
+    if (!col_ok(c0 + c)) return;
     int l = q;
     if constexpr (S < 0) {
       l = pos_band<N>(q);
@@ -183,8 +189,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
 template <typename T, int N>
 __global__ void __launch_bounds__(kThreads) k_zfwd_rhs(const RhsArgs<T> a) {
   constexpr int C = col_width<T, N>();
-  constexpr int NH = Band<N>::NH, NBB = Band<N>::NB;
-  constexpr int NCOLS = NBB * NH;
+  constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
+  constexpr int NCOLS = NBB * NHP;  // flattened (ky, kx) over the padded pitch
   using LP = LastPass<N, C, kThreads>;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
@@ -216,8 +222,9 @@ __global__ void __launch_bounds__(kThreads) k_zfwd_rhs(const RhsArgs<T> a) {
     // MHD1: R_rho = -i k . m^ (state fields 1..3, already band-limited)
     for (int e = tid; e < NBB * C; e += kThreads) {
       const int l = e / C, c = e - (e / C) * C, col = c0 + c;
-      if (col < NCOLS) {
-        const int kz = band_k<N>(l), ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+      const int kx = col - (col / NHP) * NHP;
+      if (col < NCOLS && kx < NH) {
+        const int kz = band_k<N>(l), ky = band_k<N>(col / NHP);
         const int64_t idx = (int64_t)l * LS + col;
         const cx<T> mx = ld(a.state, 1 * sc + idx), my = ld(a.state, 2 * sc + idx), mz = ld(a.state, 3 * sc + idx);
         const T dx = T(kx) * mx.x + T(ky) * my.x + T(kz) * mz.x;
@@ -244,8 +251,9 @@ __global__ void __launch_bounds__(kThreads) k_zfwd_rhs(const RhsArgs<T> a) {
     auto load = [&](int c, int q) -> cx<T> {
       const int col = c0 + c;
       cx<T> v = mk<T>(0, 0);
-      if (col >= NCOLS) return v;
-      const int ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+      const int kx = col - (col / NHP) * NHP;
+      if (col >= NCOLS || kx >= NH) return v;
+      const int ky = band_k<N>(col / NHP);
       const int64_t idx = (int64_t)q * LS + col;
       const cx<T> x0 = ld(p0, idx);
       const cx<T> x1 = nt > 1 ? ld(p1, idx) : mk<T>(0, 0);
@@ -287,8 +295,9 @@ __global__ void __launch_bounds__(kThreads) k_zfwd_rhs(const RhsArgs<T> a) {
     const int c = w % C, j = w / C;
     if (LP::TOT % kThreads != 0 && w >= LP::TOT) continue;
     const int col = c0 + c;
-    if (col >= NCOLS) continue;
-    const int ky = band_k<N>(col / NH), kx = col - (col / NH) * NH;
+    const int kx = col - (col / NHP) * NHP;
+    if (col >= NCOLS || kx >= NH) continue;
+    const int ky = band_k<N>(col / NHP);
 #pragma unroll
     for (int r = 0; r < LP::R; ++r) {
       const int l = pos_band<N>(j + r * LP::NBF);
@@ -342,7 +351,7 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s,
 
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
-  constexpr int K = Band<N>::K, NH = Band<N>::NH;
+  constexpr int K = Band<N>::K, NH = Band<N>::NH, NHP = Band<N>::NHP;
   constexpr int NB = RowShape<MODE>::NB;
   constexpr int BS = N + 1;  // padded row pitch in LDS
   __shared__ cx<T> buf[NB * BS];
@@ -381,8 +390,8 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
       if (q > K && q < N - K) return mk<T>(0, 0);
       const int k = q <= K ? q : N - q;
       const T* src = in0 + 2 * fld * ist;
-      const cx<T> x0 = ld(src, row0 * NH + k);
-      const cx<T> x1 = ld(src, (row0 + 1) * NH + k);
+      const cx<T> x0 = ld(src, row0 * NHP + k);
+      const cx<T> x1 = ld(src, (row0 + 1) * NHP + k);
       if (q == 0) return mk<T>(x0.x, x1.x);
       if (q <= K) return mk<T>(x0.x - x1.y, x0.y + x1.x);
       return mk<T>(x0.x + x1.y, x1.x - x0.y);
@@ -550,8 +559,8 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
       const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
       const cx<T> x1 = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
       T* dst = out0 + 2 * fld * ost;
-      st(dst, row0 * NH + k, x0);
-      st(dst, (row0 + 1) * NH + k, x1);
+      st(dst, row0 * NHP + k, x0);
+      st(dst, (row0 + 1) * NHP + k, x1);
     }
   }
 }

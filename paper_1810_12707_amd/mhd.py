@@ -24,7 +24,7 @@ MHD_FLAG_CHECK_CFL = 1
 
 EXPORTED = (
     "mhd_supported_size", "mhd_workspace_bytes", "mhd_init", "mhd_set_state", "mhd_get_state",
-    "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_destroy",
+    "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_spectrum_pitch", "mhd_destroy",
     "mhd_status_string", "mhd_last_error", "mhd_profile", "mhd_profile_read", "mhd_step_bytes",
 )
 
@@ -88,6 +88,8 @@ def lib() -> ctypes.CDLL:
         L.mhd_fft3d.argtypes = [vp, ctypes.c_int32, vp, vp]
         L.mhd_spectrum_size.argtypes = [ctypes.c_int32]
         L.mhd_spectrum_size.restype = ctypes.c_int64
+        L.mhd_spectrum_pitch.argtypes = [ctypes.c_int32]
+        L.mhd_spectrum_pitch.restype = ctypes.c_int32
         L.mhd_destroy.argtypes = [vp]
         L.mhd_status_string.argtypes = [ctypes.c_int]
         L.mhd_status_string.restype = ctypes.c_char_p
@@ -128,6 +130,10 @@ def mhd_workspace_bytes(p: mhd_params) -> int:
 
 def mhd_spectrum_size(n: int) -> int:
     return int(lib().mhd_spectrum_size(int(n)))
+
+
+def mhd_spectrum_pitch(n: int) -> int:
+    return int(lib().mhd_spectrum_pitch(int(n)))
 
 
 def _dtype_code(t) -> int:
@@ -265,11 +271,16 @@ class Solver:
     def diagnostics(self) -> tuple[int, dict]:
         return mhd_diagnostics(self.ctx)
 
+    @property
+    def spectrum_pitch(self) -> int:
+        return mhd_spectrum_pitch(self.n)
+
     def fft_forward(self, f):
-        """Real n^3 field (working precision) -> compact spectrum, complex view."""
+        """Real n^3 field (working precision) -> compact spectrum (flat, interleaved,
+        kx pitch `spectrum_pitch`; padding entries are left unwritten)."""
         n = self.n
         assert f.is_cuda and f.is_contiguous() and tuple(f.shape) == (n, n, n) and f.dtype == self.real_dtype
-        out = self.torch.empty(2 * self.spectrum_size, dtype=self.real_dtype, device=self.device)
+        out = self.torch.zeros(2 * self.spectrum_size, dtype=self.real_dtype, device=self.device)
         mhd_fft3d(self.ctx, -1, f, out)
         return out
 

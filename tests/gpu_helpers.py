@@ -24,14 +24,26 @@ def compact_from_full(F):
     return F[np.ix_(idx, idx, np.arange(K + 1))]
 
 
+def pitch(n):
+    K = (n - 1) // 3
+    return (K + 1 + 7) // 8 * 8
+
+
 def compact_from_flat(a, n):
+    """Flat interleaved compact spectrum (kx pitch padded) -> [nb][nb][K+1]."""
     K, nb, _ = band(n)
-    a = np.asarray(a, dtype=np.float64).reshape(nb, nb, K + 1, 2)
+    a = np.asarray(a, dtype=np.float64).reshape(nb, nb, pitch(n), 2)[:, :, :K + 1]
     return a[..., 0] + 1j * a[..., 1]
 
 
-def flat_from_compact(c):
-    return np.stack([c.real, c.imag], axis=-1).ravel()
+def flat_from_compact(c, fill=0.0):
+    """[nb][nb][K+1] -> flat interleaved with the padded kx pitch; padding set to `fill`."""
+    n_b, _, nh = c.shape
+    n = 3 * (nh - 1) + 1  # any n with this K gives the same pitch
+    out = np.full((n_b, n_b, pitch(n), 2), fill, dtype=np.float64)
+    out[:, :, :nh, 0] = c.real
+    out[:, :, :nh, 1] = c.imag
+    return out.ravel()
 
 
 def rel_l2(a, b):
