@@ -154,7 +154,16 @@ __device__ __forceinline__ void lane_map(int w, int& b, int& j) {
 }
 
 // One Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0>
+// LDS element address of (sequence b, position pos).  PADSH > 0 inserts one
+// padding slot after every 2^PADSH positions, which spreads the strided
+// Stockham writes of row-major sequences over the LDS banks.
+template <int ES, int BS, int PADSH>
+__device__ __forceinline__ int lds_at(int b, int pos) {
+  if constexpr (PADSH > 0) return b * BS + pos * ES + (pos >> PADSH);
+  else return b * BS + pos * ES;
+}
+
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0, int PADSH = 0>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   constexpr int R = Plan<N>::r[P];
   constexpr int NS = plan_ns<N>(P);
@@ -169,7 +178,7 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
     lane_map<NB, NBF, MAP>(w, b, j);
     if ((TOT % NT == 0 || w < TOT) && b < b_act) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[b * BS + (j + r * NBF) * ES];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
       if constexpr (NS > 1) {
         const int k = j % NS;
 #pragma unroll
@@ -191,18 +200,18 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
       const int k = j % NS;
       const int d = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[b * BS + (d + r * NS) * ES] = v[i][r];
+      for (int r = 0; r < R; ++r) buf[lds_at<ES, BS, PADSH>(b, d + r * NS)] = v[i][r];
     }
   }
   __syncthreads();
 }
 
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int P = 0>
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, int P = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   static_assert(plan_ok<N>(), "radix plan does not multiply to N");
   if constexpr (P < Plan<N>::np) {
-    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP>(buf, tw, tid, b_act);
-    lds_fft<T, N, NB, NT, ES, BS, S, MAP, P + 1>(buf, tw, tid, b_act);
+    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
+    lds_fft<T, N, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
   }
 }
 
@@ -213,15 +222,16 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, in
 // arithmetic, so their memory requests are in flight together.  For one-pass
 // plans the inputs go straight from load() through the DFT to store().
 // The LDS buffer may be reused after this returns only past a __syncthreads().
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int P>
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, int P>
 __device__ __forceinline__ void fft_mid_passes(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   if constexpr (P < Plan<N>::np - 1) {
-    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP>(buf, tw, tid, b_act);
-    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, P + 1>(buf, tw, tid, b_act);
+    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
+    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
   }
 }
 
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, class Load, class Store>
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, class Load,
+          class Store>
 __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Load&& load,
                                         Store&& store) {
   static_assert(plan_ok<N>(), "radix plan does not multiply to N");
@@ -253,7 +263,7 @@ __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, in
           for (int r = 0; r < R; ++r) store(i, r, b, r, v[i][r]);
         } else {
 #pragma unroll
-          for (int r = 0; r < R; ++r) buf[b * BS + (j * R + r) * ES] = v[i][r];
+          for (int r = 0; r < R; ++r) buf[lds_at<ES, BS, PADSH>(b, j * R + r)] = v[i][r];
         }
       }
     }
@@ -261,7 +271,7 @@ __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, in
     __syncthreads();
   }
   if constexpr (NP > 1) {
-    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, 1>(buf, tw, tid, b_act);
+    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, PADSH, 1>(buf, tw, tid, b_act);
     constexpr int PL = NP - 1;
     constexpr int R = Plan<N>::r[PL];
     constexpr int NS = plan_ns<N>(PL);  // = N / R
@@ -276,7 +286,7 @@ __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, in
       if ((TOT % NT == 0 || w < TOT) && b < b_act) {
         cx<T> v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = buf[b * BS + (j + r * NBF) * ES];
+        for (int r = 0; r < R; ++r) v[r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           const cx<T> t = tw[j * r];  // k = j mod NS = j; index k r N/(NS R) = j r

@@ -130,7 +130,7 @@ k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restr
   }
 }
 
-__global__ void k_fill(double* p, int n, double v) {
+__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
@@ -143,7 +143,8 @@ using namespace mhd;
 
 namespace {
 
-constexpr int kStatusWords = 4;  // [0] max CFL speed seen by steps, [1] non-finite seen
+constexpr int kStatusWords = 4;  // u32: [0] max CFL speed seen by steps (float bits), [1] non-finite count,
+                                 // [2..3] the same for pure RHS evaluations (not reported)
 constexpr int kResWords = 32;    // reduced diagnostics
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -276,7 +277,8 @@ struct Engine {
   T* iy(int slot) const { return at(c->L.iy) + 2 * (size_t)slot * g.iy; }
   T* spec_field(T* base, int f) const { return base + 2 * (size_t)f * g.sc; }
   double* part() const { return reinterpret_cast<double*>(c->ws + c->L.part); }
-  double* status() const { return reinterpret_cast<double*>(c->ws + c->L.status); }
+  unsigned* status() const { return reinterpret_cast<unsigned*>(c->ws + c->L.status); }
+  unsigned* scratch_status() const { return status() + 2; }
   double* res() const { return reinterpret_cast<double*>(c->ws + c->L.res); }
 
   // Algorithmic HBM bytes of one launch: each array read or written once,
@@ -294,10 +296,10 @@ struct Engine {
       case MHD_PASS_ZFWD_A: return cbytes(3, 3, 0);
       case MHD_PASS_ZINV_B: return cbytes(7, 12, 0);
       case MHD_PASS_YINV_B: return cbytes(0, 12, 12);
-      case MHD_PASS_XB: return cbytes(0, 0, 28) + (double)g.n * g.n * sizeof(double);
+      case MHD_PASS_XB: return cbytes(0, 0, 28);
       case MHD_PASS_YFWD_B: return cbytes(0, 12, 12);
       case MHD_PASS_ZRHS: return cbytes(32, 12, 0);
-      case MHD_PASS_REDUCE: return (double)g.n * g.n * sizeof(double);
+      case MHD_PASS_REDUCE: return 0.0;
       default: return 0.0;
     }
   }
@@ -474,15 +476,10 @@ struct Engine {
     RowArgs<T> r = row_args();
     set_in(r, 0);
     set_out(r, 0);
-    r.partials = part();
+    // the step's CFL speed and non-finite count fold into the status words; a
+    // pure RHS evaluation writes them to a scratch pair instead
+    r.status = rout ? scratch_status() : status();
     timed(MHD_PASS_XB, [&] { k.row(RM_XB, r, row_grid(), c->stream); });
-    if (!rout) {
-      // per-step CFL speed and non-finite count, merged into the status words
-      timed(MHD_PASS_REDUCE, [&] {
-        hipLaunchKernelGGL(k_reduce, dim3(2), dim3(kThreads), 0, c->stream, part(), (int64_t)g.n * g.n / 2, 2,
-                           1u | 2u, 1, status());
-      });
-    }
     T* fi[12];
     T* fo[12];
     for (int f = 0; f < 12; ++f) { fi[f] = iy(f); fo[f] = iz(f); }
@@ -524,7 +521,7 @@ struct Engine {
   }
 
   void reset_status() {
-    hipLaunchKernelGGL(k_fill, dim3(1), dim3(kStatusWords), 0, c->stream, status(), kStatusWords, 0.0);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kStatusWords), 0, c->stream, status(), kStatusWords, 0u);
   }
 
   // Diagnostics pass over the state: real-space partials and spectral sums.
@@ -737,7 +734,7 @@ int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) {
   });
   if (rc != MHD_OK) return rc;
   double res[kResWords];
-  double st[kStatusWords];
+  unsigned st[kStatusWords];
   hipError_t err = hipMemcpyAsync(res, c->ws + c->L.res, sizeof(res), hipMemcpyDeviceToHost, c->stream);
   if (err == hipSuccess)
     err = hipMemcpyAsync(st, c->ws + c->L.status, sizeof(st), hipMemcpyDeviceToHost, c->stream);
@@ -775,9 +772,11 @@ int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) {
   h->mach_s = umean / h->c_s;
   h->mach_a = h->v_a > 0 ? umean / h->v_a : INFINITY;
   h->nonfinite = (int64_t)res[DQ_NONFINITE];
-  if (h->nonfinite > 0 || st[1] > 0 || !(st[0] == st[0])) return MHD_E_NONFINITE;
-  if ((c->p.flags & MHD_FLAG_CHECK_CFL) && st[0] > 0) {
-    const double dt_lim = c->p.cfl * (two_pi / g.n) / st[0];
+  float cmax_seen;
+  std::memcpy(&cmax_seen, &st[0], sizeof(float));
+  if (h->nonfinite > 0 || st[1] > 0 || !(cmax_seen == cmax_seen)) return MHD_E_NONFINITE;
+  if ((c->p.flags & MHD_FLAG_CHECK_CFL) && cmax_seen > 0) {
+    const double dt_lim = c->p.cfl * (two_pi / g.n) / (double)cmax_seen;
     if (c->p.dt > dt_lim) return MHD_E_CFL;
   }
   return MHD_OK;

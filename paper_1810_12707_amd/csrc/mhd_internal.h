@@ -98,7 +98,8 @@ struct RowArgs {
   int32_t real_dtype;       // 0 = double, 1 = float
   int32_t nf;               // fields of an I/O pass
   double gamma, nu, eta;
-  double* partials;         // per-block records
+  double* partials;         // per-block records (RM_XDIAG)
+  unsigned* status;         // [0] max CFL speed (float bits), [1] non-finite count (RM_XB)
   const T* tw;
   Geo g;
 };

@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
 // ------------------------------------------------------------------ k_zfwd_rhs
 // Flat grid over (column tile of (ky, kx), output field f = 0..7), field fastest.
 template <typename T, int N>
-__global__ void __launch_bounds__(kThreads) k_zfwd_rhs(const RhsArgs<T> a) {
+__global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
   constexpr int C = col_width<T, N>();
   constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
   constexpr int NCOLS = NBB * NHP;  // flattened (ky, kx) over the padded pitch
@@ -353,7 +353,9 @@ template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
   constexpr int K = Band<N>::K, NH = Band<N>::NH, NHP = Band<N>::NHP;
   constexpr int NB = RowShape<MODE>::NB;
-  constexpr int BS = N + 1;  // padded row pitch in LDS
+  constexpr int PADSH = 3;                    // one LDS padding slot per 8 elements
+  constexpr int BS = N + (N >> PADSH) + 1;   // padded row pitch in LDS
+  auto at = [](int b, int pos) { return lds_at<1, BS, PADSH>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
@@ -376,7 +378,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
         r0 = T(static_cast<const float*>(a.real_in)[base]);
         r1 = T(static_cast<const float*>(a.real_in)[base + N]);
       }
-      buf[fld * BS + x] = mk<T>(r0, r1);
+      buf[at(fld, x)] = mk<T>(r0, r1);
     }
     __syncthreads();
   } else {
@@ -396,15 +398,15 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
       if (q <= K) return mk<T>(x0.x - x1.y, x0.y + x1.x);
       return mk<T>(x0.x + x1.y, x1.x - x0.y);
     };
-    auto store = [&](int, int, int fld, int q, cx<T> v) { buf[fld * BS + q] = v; };
-    fft_reg<T, N, NB, kThreads, 1, BS, +1, 1>(buf, stw, tid, nin, load, store);
+    auto store = [&](int, int, int fld, int q, cx<T> v) { buf[at(fld, q)] = v; };
+    fft_reg<T, N, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, load, store);
     __syncthreads();
   }
 
   if constexpr (MODE == RM_XINV_REAL) {
     for (int e = tid; e < nout * N; e += kThreads) {
       const int fld = e / N, x = e - (e / N) * N;
-      const cx<T> z = buf[fld * BS + x];
+      const cx<T> z = buf[at(fld, x)];
       const int64_t base = fld * a.g.n3 + row0 * N + x;
       if (a.real_dtype == 0) {
         static_cast<double*>(a.real_out)[base] = double(z.x);
@@ -420,12 +422,12 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
   if constexpr (MODE == RM_XA) {
     // u = m / rho, both rows at once
     for (int x = tid; x < N; x += kThreads) {
-      const cx<T> rho = buf[0 * BS + x];
+      const cx<T> rho = buf[at(0, x)];
       const T i0 = T(1) / rho.x, i1 = T(1) / rho.y;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const cx<T> m = buf[(1 + i) * BS + x];
-        buf[i * BS + x] = mk<T>(m.x * i0, m.y * i1);
+        const cx<T> m = buf[at(1 + i, x)];
+        buf[at(i, x)] = mk<T>(m.x * i0, m.y * i1);
       }
     }
   }
@@ -441,7 +443,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
     for (int x = tid; x < N; x += kThreads) {
       cx<T> v[16];
 #pragma unroll
-      for (int f = 0; f < 16; ++f) v[f] = buf[f * BS + x];
+      for (int f = 0; f < 16; ++f) v[f] = buf[at(f, x)];
       cx<T> o[12];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -489,15 +491,20 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
         bad += fin ? 0 : 1;
       }
 #pragma unroll
-      for (int q = 0; q < 12; ++q) buf[q * BS + x] = o[q];
+      for (int q = 0; q < 12; ++q) buf[at(q, x)] = o[q];
     }
-    // per-block CFL max and non-finite count (deterministic tree reduction)
+    // Fold the block's CFL speed and non-finite count into the status words:
+    // an unsigned max over the bit patterns of non-negative floats orders them
+    // like the floats (NaN sorts above every finite value), and integer adds
+    // commute, so the result does not depend on the order of the blocks.
     __shared__ double s_red[kThreads];
     const double cfl_b = block_reduce(double(cfl), true, s_red, tid);
     const double bad_b = block_reduce(double(bad), false, s_red, tid);
     if (tid == 0) {
-      a.partials[2 * (int64_t)p + 0] = cfl_b;
-      a.partials[2 * (int64_t)p + 1] = bad_b;
+      const float cf = float(cfl_b);
+      const unsigned bits = (cf != cf) ? 0x7fc00000u : (cf > 0.f ? __float_as_uint(cf) : 0u);
+      atomicMax(&a.status[0], bits);
+      if (bad_b > 0) atomicAdd(&a.status[1], (unsigned)bad_b);
     }
   }
 
@@ -510,7 +517,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
     for (int x = tid; x < N; x += kThreads) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        auto g = [&](int f) -> double { const cx<T> v = buf[f * BS + x]; return double(h == 0 ? v.x : v.y); };
+        auto g = [&](int f) -> double { const cx<T> v = buf[at(f, x)]; return double(h == 0 ? v.x : v.y); };
         const double rho = g(0), mx = g(1), my = g(2), mz = g(3), Bx = g(4), By = g(5), Bz = g(6), E = g(7);
         const double Jx = g(8), Jy = g(9), Jz = g(10), dB = g(11);
         const double ux = mx / rho, uy = my / rho, uz = mz / rho;
@@ -548,14 +555,14 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
 
   if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
     __syncthreads();
-    lds_fft<T, N, NB, kThreads, 1, BS, -1, 1>(buf, stw, tid, nout);
+    lds_fft<T, N, NB, kThreads, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
     // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
     T* out0 = a.out0;
     const int64_t ost = a.out_stride;
     for (int e = tid; e < nout * NH; e += kThreads) {
       const int fld = e / NH, k = e - (e / NH) * NH;
-      const cx<T> zk = buf[fld * BS + k];
-      const cx<T> zm = buf[fld * BS + (k == 0 ? 0 : N - k)];
+      const cx<T> zk = buf[at(fld, k)];
+      const cx<T> zm = buf[at(fld, k == 0 ? 0 : N - k)];
       const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
       const cx<T> x1 = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
       T* dst = out0 + 2 * fld * ost;
