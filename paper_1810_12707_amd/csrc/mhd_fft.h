@@ -153,7 +153,6 @@ __device__ __forceinline__ void lane_map(int w, int& b, int& j) {
   }
 }
 
-// One Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
 // LDS element address of (sequence b, position pos).  PADSH > 0 inserts one
 // padding slot after every 2^PADSH positions, which spreads the strided
 // Stockham writes of row-major sequences over the LDS banks.
@@ -163,6 +162,7 @@ __device__ __forceinline__ int lds_at(int b, int pos) {
   else return b * BS + pos * ES;
 }
 
+// One Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
 template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0, int PADSH = 0>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   constexpr int R = Plan<N>::r[P];
@@ -215,13 +215,7 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, in
   }
 }
 
-// Register-ended FFT: the first pass takes its inputs from load(b, pos)
-// (global memory) and the last pass hands its outputs to
-// store(i, r, b, pos, value) from registers; only the passes in between go
-// through LDS.  load() is called for all CNT*R elements of a thread before any
-// arithmetic, so their memory requests are in flight together.  For one-pass
-// plans the inputs go straight from load() through the DFT to store().
-// The LDS buffer may be reused after this returns only past a __syncthreads().
+// Passes 1 .. np-2 of a plan, LDS to LDS.
 template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, int P>
 __device__ __forceinline__ void fft_mid_passes(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   if constexpr (P < Plan<N>::np - 1) {
@@ -230,46 +224,47 @@ __device__ __forceinline__ void fft_mid_passes(cx<T>* buf, const cx<T>* tw, int 
   }
 }
 
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, class Load,
-          class Store>
-__device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Load&& load,
-                                        Store&& store) {
-  static_assert(plan_ok<N>(), "radix plan does not multiply to N");
+// Shape of the first pass of a plan: R0 elements per butterfly, CNT0
+// butterflies per thread.
+template <int N, int NB, int NT> struct FirstPass {
+  static constexpr int R = Plan<N>::r[0];
+  static constexpr int NBF = N / R;
+  static constexpr int TOT = NB * NBF;
+  static constexpr int CNT = (TOT + NT - 1) / NT;
+};
+
+// First pass from values already in registers (v[i][r] = element j + r*NBF of
+// sequence b for this thread's i-th butterfly): R-point DFTs, then either the
+// final outputs (one-pass plans) or the LDS writes of the next pass, followed
+// by a barrier.
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
+__device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<N, NB, NT>::CNT][Plan<N>::r[0]],
+                                               int tid, int b_act, Store&& store) {
+  using FP = FirstPass<N, NB, NT>;
   constexpr int NP = Plan<N>::np;
-  {
-    constexpr int R = Plan<N>::r[0];
-    constexpr int NBF = N / R;
-    constexpr int TOT = NB * NBF;
-    constexpr int CNT = (TOT + NT - 1) / NT;
-    cx<T> v[CNT][R];
 #pragma unroll
-    for (int i = 0; i < CNT; ++i) {
-      const int w = tid + i * NT;
-      int b, j;
-      lane_map<NB, NBF, MAP>(w, b, j);
-      const bool ok = (TOT % NT == 0 || w < TOT) && b < b_act;
+  for (int i = 0; i < FP::CNT; ++i) {
+    const int w = tid + i * NT;
+    int b, j;
+    lane_map<NB, FP::NBF, MAP>(w, b, j);
+    if ((FP::TOT % NT == 0 || w < FP::TOT) && b < b_act) {
+      dft<FP::R, S>(v[i]);
+      if constexpr (NP == 1) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = ok ? load(b, j + r * NBF) : mk<T>(0, 0);
-    }
+        for (int r = 0; r < FP::R; ++r) store(i, r, b, r, v[i][r]);
+      } else {
 #pragma unroll
-    for (int i = 0; i < CNT; ++i) {
-      const int w = tid + i * NT;
-      int b, j;
-      lane_map<NB, NBF, MAP>(w, b, j);
-      if ((TOT % NT == 0 || w < TOT) && b < b_act) {
-        dft<R, S>(v[i]);
-        if constexpr (NP == 1) {
-#pragma unroll
-          for (int r = 0; r < R; ++r) store(i, r, b, r, v[i][r]);
-        } else {
-#pragma unroll
-          for (int r = 0; r < R; ++r) buf[lds_at<ES, BS, PADSH>(b, j * R + r)] = v[i][r];
-        }
+        for (int r = 0; r < FP::R; ++r) buf[lds_at<ES, BS, PADSH>(b, j * FP::R + r)] = v[i][r];
       }
     }
-    if constexpr (NP == 1) return;
-    __syncthreads();
   }
+  if constexpr (NP > 1) __syncthreads();
+}
+
+// Middle passes (LDS to LDS) and the last pass (LDS to store()).
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
+__device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Store&& store) {
+  constexpr int NP = Plan<N>::np;
   if constexpr (NP > 1) {
     fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, PADSH, 1>(buf, tw, tid, b_act);
     constexpr int PL = NP - 1;
@@ -298,6 +293,33 @@ __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, in
       }
     }
   }
+}
+
+// Register-ended FFT: the first pass takes its inputs from load(b, pos)
+// (global memory) and the last pass hands its outputs to
+// store(i, r, b, pos, value) from registers; only the passes in between go
+// through LDS.  load() is called for all CNT*R elements of a thread before any
+// arithmetic, so their memory requests are in flight together.  For one-pass
+// plans the inputs go straight from load() through the DFT to store().
+// The LDS buffer may be reused after this returns only past a __syncthreads().
+template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, class Load,
+          class Store>
+__device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Load&& load,
+                                        Store&& store) {
+  static_assert(plan_ok<N>(), "radix plan does not multiply to N");
+  using FP = FirstPass<N, NB, NT>;
+  cx<T> v[FP::CNT][FP::R];
+#pragma unroll
+  for (int i = 0; i < FP::CNT; ++i) {
+    const int w = tid + i * NT;
+    int b, j;
+    lane_map<NB, FP::NBF, MAP>(w, b, j);
+    const bool ok = (FP::TOT % NT == 0 || w < FP::TOT) && b < b_act;
+#pragma unroll
+    for (int r = 0; r < FP::R; ++r) v[i][r] = ok ? load(b, j + r * FP::NBF) : mk<T>(0, 0);
+  }
+  fft_first_regs<T, N, NB, NT, ES, BS, S, MAP, PADSH>(buf, v, tid, b_act, store);
+  fft_rest<T, N, NB, NT, ES, BS, S, MAP, PADSH>(buf, tw, tid, b_act, store);
 }
 
 // Per-thread shape of the last pass of fft_reg (for callers that keep its

@@ -215,6 +215,8 @@ struct mhd_ctx {
   bool first_step;
   int64_t step;
   double t;
+  int num_cus = 0;
+  int row_blocks[5] = {0, 0, 0, 0, 0};  // persistent grid of each row-pass mode
   std::string last_err;
   // benchmark timing (mhd_profile)
   bool prof_on = false;
@@ -365,7 +367,8 @@ struct Engine {
     return a;
   }
 
-  dim3 row_grid() const { return dim3((unsigned)((int64_t)g.n * g.n / 2)); }
+  // Persistent row passes: as many workgroups as can be resident at once.
+  dim3 row_grid(int mode) const { return dim3((unsigned)c->row_blocks[mode]); }
 
   // Row passes address consecutive I_y slots from a first slot and a stride.
   void set_in(RowArgs<T>& r, int first_slot) const {
@@ -386,7 +389,7 @@ struct Engine {
     r.real_dtype = dtype == MHD_FP64 ? 0 : 1;
     r.nf = nf;
     set_out(r, 0);
-    k.row(RM_XFWD_REAL, r, row_grid(), c->stream);
+    k.row(RM_XFWD_REAL, r, row_grid(RM_XFWD_REAL), c->stream);
     T* yi[kMaxOut];
     T* yo[kMaxOut];
     for (int f = 0; f < nf; ++f) { yi[f] = iy(f); yo[f] = iz(f); }
@@ -417,7 +420,7 @@ struct Engine {
     r.real_dtype = dtype == MHD_FP64 ? 0 : 1;
     r.nf = nf;
     set_in(r, 0);
-    k.row(RM_XINV_REAL, r, row_grid(), c->stream);
+    k.row(RM_XINV_REAL, r, row_grid(RM_XINV_REAL), c->stream);
   }
 
   // Phase A: u^ = D F[m / rho] from the state U.
@@ -436,7 +439,7 @@ struct Engine {
     RowArgs<T> r = row_args();
     set_in(r, 0);
     set_out(r, 4);
-    timed(MHD_PASS_XA, [&] { k.row(RM_XA, r, row_grid(), c->stream); });
+    timed(MHD_PASS_XA, [&] { k.row(RM_XA, r, row_grid(RM_XA), c->stream); });
     T* ui[3] = {iy(4), iy(5), iy(6)};
     T* uo[3] = {iz(0), iz(1), iz(2)};
     timed(MHD_PASS_YFWD_A, [&] { y_copy(PK_YFWD, 3, ui, uo); });
@@ -479,7 +482,7 @@ struct Engine {
     // the step's CFL speed and non-finite count fold into the status words; a
     // pure RHS evaluation writes them to a scratch pair instead
     r.status = rout ? scratch_status() : status();
-    timed(MHD_PASS_XB, [&] { k.row(RM_XB, r, row_grid(), c->stream); });
+    timed(MHD_PASS_XB, [&] { k.row(RM_XB, r, row_grid(RM_XB), c->stream); });
     T* fi[12];
     T* fo[12];
     for (int f = 0; f < 12; ++f) { fi[f] = iy(f); fo[f] = iz(f); }
@@ -546,9 +549,9 @@ struct Engine {
     RowArgs<T> r = row_args();
     set_in(r, 0);
     r.partials = part();
-    k.row(RM_XDIAG, r, row_grid(), c->stream);
+    k.row(RM_XDIAG, r, row_grid(RM_XDIAG), c->stream);
     const unsigned maxmask = (1u << DQ_DIVB_MAX) | (1u << DQ_CFL_MAX);
-    hipLaunchKernelGGL(k_reduce, dim3(kDiagQ), dim3(kThreads), 0, c->stream, part(), (int64_t)g.n * g.n / 2,
+    hipLaunchKernelGGL(k_reduce, dim3(kDiagQ), dim3(kThreads), 0, c->stream, part(), (int64_t)c->row_blocks[RM_XDIAG],
                        kDiagQ, maxmask, 0, res());
     const int sblocks = (int)((g.sc + kThreads - 1) / kThreads);
     hipLaunchKernelGGL((k_spec_diag<T>), dim3(sblocks), dim3(kThreads), 0, c->stream, spec_field(U, 4),
@@ -635,9 +638,27 @@ int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_
   c->first_step = true;
   c->step = 0;
   c->t = 0.0;
-  if (!kern_for(c)) {
+  const void* kv = kern_for(c);
+  if (!kv) {
     delete c;
     return MHD_E_SIZE;
+  }
+  {
+    int dev = 0;
+    hipError_t e0 = hipGetDevice(&dev);
+    if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e0 != hipSuccess || c->num_cus <= 0) {
+      delete c;
+      return MHD_E_HIP;
+    }
+    const int64_t rows = (int64_t)p->n * p->n / 2;
+    for (int m = 0; m < 5; ++m) {
+      const int occ = p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->row_occupancy(m)
+                                               : static_cast<const Kern<double>*>(kv)->row_occupancy(m);
+      int64_t blocks = (int64_t)occ * c->num_cus;
+      if (blocks > rows) blocks = rows;
+      c->row_blocks[m] = (int)blocks;
+    }
   }
   // twiddles exp(-2 pi i j / n) in FP64, rounded once to the working precision
   const int n = p->n;

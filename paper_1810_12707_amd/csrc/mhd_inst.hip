@@ -35,6 +35,25 @@ void row(int mode, const RowArgs<T>& a, dim3 g, hipStream_t s) {
 }
 
 template <typename T, int N>
+int row_occupancy(int mode) {
+  int blocks = 0;
+  hipError_t e = hipSuccess;
+  switch (mode) {
+    case RM_XA: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XA>, kThreads, 0); break;
+    case RM_XB: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XB>, kThreads, 0); break;
+    case RM_XFWD_REAL:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XFWD_REAL>, kThreads, 0);
+      break;
+    case RM_XINV_REAL:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XINV_REAL>, kThreads, 0);
+      break;
+    case RM_XDIAG: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XDIAG>, kThreads, 0); break;
+    default: break;
+  }
+  return (e == hipSuccess && blocks > 0) ? blocks : 1;
+}
+
+template <typename T, int N>
 Kern<T> make() {
   Kern<T> k;
   k.n = N;
@@ -43,6 +62,7 @@ Kern<T> make() {
   k.col_fwd = col_fwd<T, N>;
   k.rhs = rhs<T, N>;
   k.row = row<T, N>;
+  k.row_occupancy = row_occupancy<T, N>;
   return k;
 }
 

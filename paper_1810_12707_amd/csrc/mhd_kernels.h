@@ -349,154 +349,274 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s,
   return s[0];
 }
 
+// Persistent: workgroup w handles row pairs w, w + G, w + 2G, ... (G = grid
+// size, sized by the host to the number of resident workgroups).  For the
+// spectral-input modes the global loads of the next row pair's first FFT pass
+// are issued right after the current pair's first pass, so they are in flight
+// during the current pair's LDS passes, pointwise work and stores.
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
-  constexpr int K = Band<N>::K, NH = Band<N>::NH, NHP = Band<N>::NHP;
+  constexpr int K = Band<N>::K, NHP = Band<N>::NHP;
+  constexpr int NH = Band<N>::NH;
   constexpr int NB = RowShape<MODE>::NB;
   constexpr int PADSH = 3;                    // one LDS padding slot per 8 elements
   constexpr int BS = N + (N >> PADSH) + 1;   // padded row pitch in LDS
+  constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
+  using FP = FirstPass<N, NB, kThreads>;
   auto at = [](int b, int pos) { return lds_at<1, BS, PADSH>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
-  const int p = blockIdx.x;
-  const int64_t row0 = 2 * (int64_t)p;  // flattened row index z*N + y of the first row
+  const int64_t nitems = (int64_t)N * N / 2;
   const int nin = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NIN;
   const int nout = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NOUT;
   load_twiddles<T, N>(stw, a.tw, tid);
+  auto lds_store = [&](int, int, int fld, int q, cx<T> v) { buf[at(fld, q)] = v; };
 
-  if constexpr (MODE == RM_XFWD_REAL) {
-    // real rows -> packed complex row0 + i row1
-    for (int e = tid; e < nin * N; e += kThreads) {
-      const int fld = e / N, x = e - (e / N) * N;
-      const int64_t base = fld * a.g.n3 + row0 * N + x;
-      T r0, r1;
-      if (a.real_dtype == 0) {
-        r0 = T(static_cast<const double*>(a.real_in)[base]);
-        r1 = T(static_cast<const double*>(a.real_in)[base + N]);
-      } else {
-        r0 = T(static_cast<const float*>(a.real_in)[base]);
-        r1 = T(static_cast<const float*>(a.real_in)[base + N]);
-      }
-      buf[at(fld, x)] = mk<T>(r0, r1);
-    }
-    __syncthreads();
-  } else {
-    // Inverse x transform.  The first FFT pass reads the Hermitian half rows
-    // (kx = 0..K) of both rows straight from global memory as the packed
-    // spectrum Z[q] = X0[q] + i X1[q] (q <= K), Z[N-k] = conj(X0[k]) + i conj(X1[k]);
-    // the last pass leaves the packed real rows (row0 + i row1) in LDS.
-    const T* in0 = a.in0;
-    const int64_t ist = a.in_stride;
-    auto load = [&](int fld, int q) -> cx<T> {
-      if (q > K && q < N - K) return mk<T>(0, 0);
-      const int k = q <= K ? q : N - q;
-      const T* src = in0 + 2 * fld * ist;
-      const cx<T> x0 = ld(src, row0 * NHP + k);
-      const cx<T> x1 = ld(src, (row0 + 1) * NHP + k);
-      if (q == 0) return mk<T>(x0.x, x1.x);
-      if (q <= K) return mk<T>(x0.x - x1.y, x0.y + x1.x);
-      return mk<T>(x0.x + x1.y, x1.x - x0.y);
-    };
-    auto store = [&](int, int, int fld, int q, cx<T> v) { buf[at(fld, q)] = v; };
-    fft_reg<T, N, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, load, store);
-    __syncthreads();
-  }
-
-  if constexpr (MODE == RM_XINV_REAL) {
-    for (int e = tid; e < nout * N; e += kThreads) {
-      const int fld = e / N, x = e - (e / N) * N;
-      const cx<T> z = buf[at(fld, x)];
-      const int64_t base = fld * a.g.n3 + row0 * N + x;
-      if (a.real_dtype == 0) {
-        static_cast<double*>(a.real_out)[base] = double(z.x);
-        static_cast<double*>(a.real_out)[base + N] = double(z.y);
-      } else {
-        static_cast<float*>(a.real_out)[base] = float(z.x);
-        static_cast<float*>(a.real_out)[base + N] = float(z.y);
-      }
-    }
-    return;
-  }
-
-  if constexpr (MODE == RM_XA) {
-    // u = m / rho, both rows at once
-    for (int x = tid; x < N; x += kThreads) {
-      const cx<T> rho = buf[at(0, x)];
-      const T i0 = T(1) / rho.x, i1 = T(1) / rho.y;
+  // Prefetch registers for the next row pair: the two rows' Hermitian
+  // half-spectrum entries X0[q], X1[q] behind the first-pass elements in the
+  // lower half (q < N/2, r < R/2).  Elements q >= N-K use X[N-q], which a
+  // mirror lane prefetched, so they are read when used and hit the cache.
+  constexpr int RH = FP::R / 2;
+  cx<T> p0[FP::CNT][RH], p1[FP::CNT][RH];
+  auto issue = [&](int64_t item) {
+    const int64_t row0 = 2 * item;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const cx<T> m = buf[at(1 + i, x)];
-        buf[at(i, x)] = mk<T>(m.x * i0, m.y * i1);
+    for (int i = 0; i < FP::CNT; ++i) {
+      const int w = tid + i * kThreads;
+      int b, j;
+      lane_map<NB, FP::NBF, 1>(w, b, j);
+      const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && b < nin;
+      const T* src = a.in0 + 2 * b * a.in_stride;
+#pragma unroll
+      for (int r = 0; r < RH; ++r) {
+        const int q = j + r * FP::NBF;
+        if (ok && q <= K) {
+          p0[i][r] = ld(src, row0 * NHP + q);
+          p1[i][r] = ld(src, (row0 + 1) * NHP + q);
+        }
+      }
+    }
+  };
+  // per-workgroup accumulators of the diagnostic / status modes
+  T cfl = T(0);
+  int bad = 0;
+  double q[kDiagQ];
+#pragma unroll
+  for (int i = 0; i < kDiagQ; ++i) q[i] = 0.0;
+
+  int64_t item = blockIdx.x;
+  if constexpr (SPEC_IN) {
+    if (item < nitems) issue(item);
+  }
+  for (; item < nitems; item += gridDim.x) {
+    const int64_t row0 = 2 * item;  // flattened row index z*N + y of the first row
+    __syncthreads();                // the previous row pair is done with the LDS
+    if constexpr (!SPEC_IN) {
+      // real rows -> packed complex row0 + i row1
+      for (int e = tid; e < nin * N; e += kThreads) {
+        const int fld = e / N, x = e - (e / N) * N;
+        const int64_t base = fld * a.g.n3 + row0 * N + x;
+        T r0, r1;
+        if (a.real_dtype == 0) {
+          r0 = T(static_cast<const double*>(a.real_in)[base]);
+          r1 = T(static_cast<const double*>(a.real_in)[base + N]);
+        } else {
+          r0 = T(static_cast<const float*>(a.real_in)[base]);
+          r1 = T(static_cast<const float*>(a.real_in)[base + N]);
+        }
+        buf[at(fld, x)] = mk<T>(r0, r1);
+      }
+    } else {
+      // inverse x transform: first pass from the prefetched registers
+      // first-pass inputs Z[q] = X0[q] + i X1[q] (q <= K),
+      // Z[N-k] = conj(X0[k]) + i conj(X1[k]) (k <= K), zero in the gap
+      cx<T> v[FP::CNT][FP::R];
+#pragma unroll
+      for (int i = 0; i < FP::CNT; ++i) {
+        const int w = tid + i * kThreads;
+        int b, j;
+        lane_map<NB, FP::NBF, 1>(w, b, j);
+        const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && b < nin;
+        const T* src = a.in0 + 2 * b * a.in_stride;
+#pragma unroll
+        for (int r = 0; r < FP::R; ++r) {
+          const int q = j + r * FP::NBF;
+          cx<T> x0 = mk<T>(0, 0), x1 = mk<T>(0, 0);
+          if (r < RH) {
+            x0 = p0[i][r < RH ? r : 0];
+            x1 = p1[i][r < RH ? r : 0];
+          }
+          if (ok && q >= N - K) {
+            x0 = ld(src, row0 * NHP + (N - q));
+            x1 = ld(src, (row0 + 1) * NHP + (N - q));
+          }
+          cx<T> z = mk<T>(0, 0);
+          if (ok) {
+            if (q == 0) z = mk<T>(x0.x, x1.x);
+            else if (q <= K) z = mk<T>(x0.x - x1.y, x0.y + x1.x);
+            else if (q >= N - K) z = mk<T>(x0.x + x1.y, x1.x - x0.y);
+          }
+          v[i][r] = z;
+        }
+      }
+      fft_first_regs<T, N, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, v, tid, nin, lds_store);
+      if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
+      fft_rest<T, N, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, lds_store);
+    }
+    __syncthreads();
+
+    if constexpr (MODE == RM_XINV_REAL) {
+      for (int e = tid; e < nout * N; e += kThreads) {
+        const int fld = e / N, x = e - (e / N) * N;
+        const cx<T> z = buf[at(fld, x)];
+        const int64_t base = fld * a.g.n3 + row0 * N + x;
+        if (a.real_dtype == 0) {
+          static_cast<double*>(a.real_out)[base] = double(z.x);
+          static_cast<double*>(a.real_out)[base + N] = double(z.y);
+        } else {
+          static_cast<float*>(a.real_out)[base] = float(z.x);
+          static_cast<float*>(a.real_out)[base + N] = float(z.y);
+        }
+      }
+      continue;
+    }
+
+    if constexpr (MODE == RM_XA) {
+      // u = m / rho, both rows at once
+      for (int x = tid; x < N; x += kThreads) {
+        const cx<T> rho = buf[at(0, x)];
+        const T i0 = T(1) / rho.x, i1 = T(1) / rho.y;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const cx<T> m = buf[at(1 + i, x)];
+          buf[at(i, x)] = mk<T>(m.x * i0, m.y * i1);
+        }
+      }
+    }
+
+    if constexpr (MODE == RM_XB) {
+      // Real-space fluxes of Eqs. MHD2-MHD4 at every point of both rows.
+      // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8 S_xx, 9 S_yy, 10 S_xy, 11 S_xz,
+      // 12 S_yz, 13-15 J.  Outputs: 0 Pi_xx, 1 Pi_yy, 2 Pi_zz, 3 Pi_xy,
+      // 4 Pi_xz, 5 Pi_yz, 6-8 F^E, 9-11 e = u x B.
+      const T gm1 = T(a.gamma - 1.0), gam = T(a.gamma), two_nu = T(2.0 * a.nu), eta = T(a.eta);
+      for (int x = tid; x < N; x += kThreads) {
+        cx<T> v[16];
+#pragma unroll
+        for (int f = 0; f < 16; ++f) v[f] = buf[at(f, x)];
+        cx<T> o[12];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto g = [&](int f) -> T { return h == 0 ? v[f].x : v[f].y; };
+          const T rho = g(0), mx = g(1), my = g(2), mz = g(3);
+          const T Bx = g(4), By = g(5), Bz = g(6), E = g(7);
+          const T Sxx = g(8), Syy = g(9), Sxy = g(10), Sxz = g(11), Syz = g(12);
+          const T Szz = -(Sxx + Syy);
+          const T Jx = g(13), Jy = g(14), Jz = g(15);
+          const T ir = T(1) / rho;
+          const T ux = mx * ir, uy = my * ir, uz = mz * ir;
+          const T B2 = Bx * Bx + By * By + Bz * Bz;
+          const T P = gm1 * (E - T(0.5) * (mx * ux + my * uy + mz * uz) - T(0.5) * B2);
+          const T Pt = P + T(0.5) * B2;
+          const T vr = two_nu * rho;
+          T out[12];
+          out[0] = mx * ux + Pt - Bx * Bx - vr * Sxx;
+          out[1] = my * uy + Pt - By * By - vr * Syy;
+          out[2] = mz * uz + Pt - Bz * Bz - vr * Szz;
+          out[3] = mx * uy - Bx * By - vr * Sxy;
+          out[4] = mx * uz - Bx * Bz - vr * Sxz;
+          out[5] = my * uz - By * Bz - vr * Syz;
+          const T uB = ux * Bx + uy * By + uz * Bz;
+          const T EP = E + Pt;
+          const T uSx = ux * Sxx + uy * Sxy + uz * Sxz;
+          const T uSy = ux * Sxy + uy * Syy + uz * Syz;
+          const T uSz = ux * Sxz + uy * Syz + uz * Szz;
+          out[6] = EP * ux - uB * Bx - vr * uSx - eta * (By * Jz - Bz * Jy);
+          out[7] = EP * uy - uB * By - vr * uSy - eta * (Bz * Jx - Bx * Jz);
+          out[8] = EP * uz - uB * Bz - vr * uSz - eta * (Bx * Jy - By * Jx);
+          out[9] = uy * Bz - uz * By;
+          out[10] = uz * Bx - ux * Bz;
+          out[11] = ux * By - uy * Bx;
+#pragma unroll
+          for (int k = 0; k < 12; ++k) {
+            if (h == 0) o[k].x = out[k];
+            else o[k].y = out[k];
+          }
+          // fastest signal speed for the CFL limit, and a non-finite check
+          const T umax = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
+          const T c = umax + sqrt((gam * P + B2) * ir);
+          if (!(c <= cfl)) cfl = c;  // NaN propagates
+          const bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) &&
+                           finite_(By) && finite_(Bz) && finite_(E);
+          bad += fin ? 0 : 1;
+        }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) buf[at(k, x)] = o[k];
+      }
+    }
+
+    if constexpr (MODE == RM_XDIAG) {
+      // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8-10 J, 11 div B.
+      const double gm1 = a.gamma - 1.0, gam = a.gamma;
+      for (int x = tid; x < N; x += kThreads) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          auto g = [&](int f) -> double { const cx<T> v = buf[at(f, x)]; return double(h == 0 ? v.x : v.y); };
+          const double rho = g(0), mx = g(1), my = g(2), mz = g(3), Bx = g(4), By = g(5), Bz = g(6), E = g(7);
+          const double Jx = g(8), Jy = g(9), Jz = g(10), dB = g(11);
+          const double ux = mx / rho, uy = my / rho, uz = mz / rho;
+          const double B2 = Bx * Bx + By * By + Bz * Bz;
+          const double mu = mx * ux + my * uy + mz * uz;
+          const double P = gm1 * (E - 0.5 * mu - 0.5 * B2);
+          q[DQ_RHO] += rho;
+          q[DQ_MX] += mx;
+          q[DQ_MY] += my;
+          q[DQ_MZ] += mz;
+          q[DQ_EKIN] += 0.5 * mu;
+          q[DQ_EMAG] += 0.5 * B2;
+          q[DQ_P] += P;
+          q[DQ_E] += E;
+          q[DQ_HC] += ux * Bx + uy * By + uz * Bz;
+          q[DQ_UABS] += sqrt(ux * ux + uy * uy + uz * uz);
+          q[DQ_BABS] += sqrt(B2);
+          const double adb = fabs(dB);
+          if (!(adb <= q[DQ_DIVB_MAX])) q[DQ_DIVB_MAX] = adb;
+          const double c = fmax(fabs(ux), fmax(fabs(uy), fabs(uz))) + sqrt((gam * P + B2) / rho);
+          if (!(c <= q[DQ_CFL_MAX])) q[DQ_CFL_MAX] = c;
+          const bool fin = isfinite(rho) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(Bx) &&
+                           isfinite(By) && isfinite(Bz) && isfinite(E);
+          q[DQ_NONFINITE] += fin ? 0.0 : 1.0;
+          q[DQ_J2] += Jx * Jx + Jy * Jy + Jz * Jz;
+        }
+      }
+      continue;
+    }
+
+    if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
+      __syncthreads();
+      lds_fft<T, N, NB, kThreads, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
+      // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
+      T* out0 = a.out0;
+      const int64_t ost = a.out_stride;
+      for (int e = tid; e < nout * NH; e += kThreads) {
+        const int fld = e / NH, k = e - (e / NH) * NH;
+        const cx<T> zk = buf[at(fld, k)];
+        const cx<T> zm = buf[at(fld, k == 0 ? 0 : N - k)];
+        const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+        const cx<T> x1 = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
+        T* dst = out0 + 2 * fld * ost;
+        st(dst, row0 * NHP + k, x0);
+        st(dst, (row0 + 1) * NHP + k, x1);
       }
     }
   }
 
   if constexpr (MODE == RM_XB) {
-    // Real-space fluxes of Eqs. MHD2-MHD4 at every point of both rows.
-    // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8 S_xx, 9 S_yy, 10 S_xy, 11 S_xz,
-    // 12 S_yz, 13-15 J.  Outputs: 0 Pi_xx, 1 Pi_yy, 2 Pi_zz, 3 Pi_xy,
-    // 4 Pi_xz, 5 Pi_yz, 6-8 F^E, 9-11 e = u x B.
-    const T gm1 = T(a.gamma - 1.0), gam = T(a.gamma), two_nu = T(2.0 * a.nu), eta = T(a.eta);
-    T cfl = T(0);
-    int bad = 0;
-    for (int x = tid; x < N; x += kThreads) {
-      cx<T> v[16];
-#pragma unroll
-      for (int f = 0; f < 16; ++f) v[f] = buf[at(f, x)];
-      cx<T> o[12];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto g = [&](int f) -> T { return h == 0 ? v[f].x : v[f].y; };
-        const T rho = g(0), mx = g(1), my = g(2), mz = g(3);
-        const T Bx = g(4), By = g(5), Bz = g(6), E = g(7);
-        const T Sxx = g(8), Syy = g(9), Sxy = g(10), Sxz = g(11), Syz = g(12);
-        const T Szz = -(Sxx + Syy);
-        const T Jx = g(13), Jy = g(14), Jz = g(15);
-        const T ir = T(1) / rho;
-        const T ux = mx * ir, uy = my * ir, uz = mz * ir;
-        const T B2 = Bx * Bx + By * By + Bz * Bz;
-        const T P = gm1 * (E - T(0.5) * (mx * ux + my * uy + mz * uz) - T(0.5) * B2);
-        const T Pt = P + T(0.5) * B2;
-        const T vr = two_nu * rho;
-        T out[12];
-        out[0] = mx * ux + Pt - Bx * Bx - vr * Sxx;
-        out[1] = my * uy + Pt - By * By - vr * Syy;
-        out[2] = mz * uz + Pt - Bz * Bz - vr * Szz;
-        out[3] = mx * uy - Bx * By - vr * Sxy;
-        out[4] = mx * uz - Bx * Bz - vr * Sxz;
-        out[5] = my * uz - By * Bz - vr * Syz;
-        const T uB = ux * Bx + uy * By + uz * Bz;
-        const T EP = E + Pt;
-        const T uSx = ux * Sxx + uy * Sxy + uz * Sxz;
-        const T uSy = ux * Sxy + uy * Syy + uz * Syz;
-        const T uSz = ux * Sxz + uy * Syz + uz * Szz;
-        out[6] = EP * ux - uB * Bx - vr * uSx - eta * (By * Jz - Bz * Jy);
-        out[7] = EP * uy - uB * By - vr * uSy - eta * (Bz * Jx - Bx * Jz);
-        out[8] = EP * uz - uB * Bz - vr * uSz - eta * (Bx * Jy - By * Jx);
-        out[9] = uy * Bz - uz * By;
-        out[10] = uz * Bx - ux * Bz;
-        out[11] = ux * By - uy * Bx;
-#pragma unroll
-        for (int q = 0; q < 12; ++q) {
-          if (h == 0) o[q].x = out[q];
-          else o[q].y = out[q];
-        }
-        // fastest signal speed for the CFL limit, and a non-finite check
-        const T umax = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
-        const T c = umax + sqrt((gam * P + B2) * ir);
-        if (!(c <= cfl)) cfl = c;  // NaN propagates
-        const bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) &&
-                         finite_(By) && finite_(Bz) && finite_(E);
-        bad += fin ? 0 : 1;
-      }
-#pragma unroll
-      for (int q = 0; q < 12; ++q) buf[at(q, x)] = o[q];
-    }
-    // Fold the block's CFL speed and non-finite count into the status words:
-    // an unsigned max over the bit patterns of non-negative floats orders them
-    // like the floats (NaN sorts above every finite value), and integer adds
-    // commute, so the result does not depend on the order of the blocks.
+    // Fold the workgroup's CFL speed and non-finite count into the status
+    // words: an unsigned max over the bit patterns of non-negative floats
+    // orders them like the floats (NaN sorts above every finite value), and
+    // integer adds commute, so the result does not depend on block order.
     __shared__ double s_red[kThreads];
     const double cfl_b = block_reduce(double(cfl), true, s_red, tid);
     const double bad_b = block_reduce(double(bad), false, s_red, tid);
@@ -507,67 +627,11 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
       if (bad_b > 0) atomicAdd(&a.status[1], (unsigned)bad_b);
     }
   }
-
   if constexpr (MODE == RM_XDIAG) {
-    // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8-10 J, 11 div B.
-    const T gm1 = T(a.gamma - 1.0), gam = T(a.gamma);
-    double q[kDiagQ];
-#pragma unroll
-    for (int i = 0; i < kDiagQ; ++i) q[i] = 0.0;
-    for (int x = tid; x < N; x += kThreads) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        auto g = [&](int f) -> double { const cx<T> v = buf[at(f, x)]; return double(h == 0 ? v.x : v.y); };
-        const double rho = g(0), mx = g(1), my = g(2), mz = g(3), Bx = g(4), By = g(5), Bz = g(6), E = g(7);
-        const double Jx = g(8), Jy = g(9), Jz = g(10), dB = g(11);
-        const double ux = mx / rho, uy = my / rho, uz = mz / rho;
-        const double B2 = Bx * Bx + By * By + Bz * Bz;
-        const double mu = mx * ux + my * uy + mz * uz;
-        const double P = double(gm1) * (E - 0.5 * mu - 0.5 * B2);
-        q[DQ_RHO] += rho;
-        q[DQ_MX] += mx;
-        q[DQ_MY] += my;
-        q[DQ_MZ] += mz;
-        q[DQ_EKIN] += 0.5 * mu;
-        q[DQ_EMAG] += 0.5 * B2;
-        q[DQ_P] += P;
-        q[DQ_E] += E;
-        q[DQ_HC] += ux * Bx + uy * By + uz * Bz;
-        q[DQ_UABS] += sqrt(ux * ux + uy * uy + uz * uz);
-        q[DQ_BABS] += sqrt(B2);
-        const double adb = fabs(dB);
-        if (!(adb <= q[DQ_DIVB_MAX])) q[DQ_DIVB_MAX] = adb;
-        const double c = fmax(fabs(ux), fmax(fabs(uy), fabs(uz))) + sqrt((double(gam) * P + B2) / rho);
-        if (!(c <= q[DQ_CFL_MAX])) q[DQ_CFL_MAX] = c;
-        const bool fin = isfinite(rho) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(Bx) &&
-                         isfinite(By) && isfinite(Bz) && isfinite(E);
-        q[DQ_NONFINITE] += fin ? 0.0 : 1.0;
-        q[DQ_J2] += Jx * Jx + Jy * Jy + Jz * Jz;
-      }
-    }
     __shared__ double s_red[kThreads];
     for (int i = 0; i < kDiagQ; ++i) {
       const double r = block_reduce(q[i], i == DQ_DIVB_MAX || i == DQ_CFL_MAX, s_red, tid);
-      if (tid == 0) a.partials[(int64_t)p * kDiagQ + i] = r;
-    }
-    return;
-  }
-
-  if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
-    __syncthreads();
-    lds_fft<T, N, NB, kThreads, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
-    // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
-    T* out0 = a.out0;
-    const int64_t ost = a.out_stride;
-    for (int e = tid; e < nout * NH; e += kThreads) {
-      const int fld = e / NH, k = e - (e / NH) * NH;
-      const cx<T> zk = buf[at(fld, k)];
-      const cx<T> zm = buf[at(fld, k == 0 ? 0 : N - k)];
-      const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
-      const cx<T> x1 = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
-      T* dst = out0 + 2 * fld * ost;
-      st(dst, row0 * NHP + k, x0);
-      st(dst, (row0 + 1) * NHP + k, x1);
+      if (tid == 0) a.partials[(int64_t)blockIdx.x * kDiagQ + i] = r;
     }
   }
 }

@@ -14,6 +14,8 @@ struct Kern {
   void (*col_fwd)(const ColArgs<T>&, dim3, hipStream_t) = nullptr;
   void (*rhs)(const RhsArgs<T>&, dim3, hipStream_t) = nullptr;
   void (*row)(int mode, const RowArgs<T>&, dim3, hipStream_t) = nullptr;
+  // resident workgroups per CU of a row-pass mode (persistent grid sizing)
+  int (*row_occupancy)(int mode) = nullptr;
 };
 
 struct Registry {
