@@ -341,4 +341,19 @@ __device__ __forceinline__ int xcd_remap(int w, int total) {
   return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
+// Item order of a persistent grid of G workgroups over `total` items: the
+// items are split into eight contiguous ranges, one per XCD, and the
+// workgroups resident on an XCD (ids w with w mod 8 = x) walk that XCD's
+// range together.  Returns the k-th item of workgroup w, or -1 when done.
+__device__ __forceinline__ int64_t xcd_item(int w, int G, int64_t k, int64_t total) {
+  constexpr int X = 8;
+  const int xcd = w % X, slot = w / X;
+  const int per = G / X + (xcd < G % X ? 1 : 0);
+  const int64_t base = total / X, rem = total % X;
+  const int64_t start = xcd * base + (xcd < rem ? xcd : rem);
+  const int64_t len = base + (xcd < rem ? 1 : 0);
+  const int64_t idx = k * per + slot;
+  return idx < len ? start + idx : -1;
+}
+
 }  // namespace mhd

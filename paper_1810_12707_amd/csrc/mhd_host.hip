@@ -217,6 +217,7 @@ struct mhd_ctx {
   double t;
   int num_cus = 0;
   int row_blocks[5] = {0, 0, 0, 0, 0};  // persistent grid of each row-pass mode
+  int col_blocks[3] = {0, 0, 0};        // column passes: forward, inverse (1 term), inverse (3 terms)
   std::string last_err;
   // benchmark timing (mhd_profile)
   bool prof_on = false;
@@ -335,17 +336,24 @@ struct Engine {
     return a;
   }
 
-  // Launch a column pass; ins/outs are per-launch slot lists.
+  // Launch a column pass; ins/outs are per-launch slot lists.  Persistent
+  // grid: resident workgroups, capped by the item count.
   void col(int kind, int nout, const T* const* ins, int nin, T* const* outs, const OutSpec* specs) {
     ColArgs<T> a = col_args(kind, nout);
     for (int i = 0; i < nin; ++i) a.in[i] = ins[i];
+    int maxt = 1;
     for (int f = 0; f < nout; ++f) {
       a.out[f] = outs[f];
       a.spec[f] = specs[f];
+      if (specs[f].nterms > maxt) maxt = specs[f].nterms;
     }
     const bool z = (kind == PK_ZINV || kind == PK_ZFWD);
-    dim3 grid((unsigned)((z ? ztiles() : g.n * ytiles()) * nout));
-    if (kind == PK_ZINV || kind == PK_YINV) k.col_inv(a, grid, c->stream);
+    const bool inv = (kind == PK_ZINV || kind == PK_YINV);
+    const int64_t items = (int64_t)(z ? ztiles() : g.n * ytiles()) * nout;
+    int64_t blocks = (int64_t)c->col_blocks[inv ? (maxt > 1 ? 2 : 1) : 0];
+    if (blocks > items) blocks = items;
+    dim3 grid((unsigned)blocks);
+    if (inv) k.col_inv(maxt, a, grid, c->stream);
     else k.col_fwd(a, grid, c->stream);
   }
 
@@ -659,6 +667,14 @@ int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_
       if (blocks > rows) blocks = rows;
       c->row_blocks[m] = (int)blocks;
     }
+    const int cocc[3] = {
+        p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(-1, 1)
+                                 : static_cast<const Kern<double>*>(kv)->col_occupancy(-1, 1),
+        p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 1)
+                                 : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 1),
+        p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 3)
+                                 : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 3)};
+    for (int m = 0; m < 3; ++m) c->col_blocks[m] = cocc[m] * c->num_cus;
   }
   // twiddles exp(-2 pi i j / n) in FP64, rounded once to the working precision
   const int n = p->n;

@@ -11,12 +11,22 @@ namespace mhd {
 namespace {
 
 template <typename T, int N>
-void col_inv(const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((k_col<T, N, 1>), g, dim3(kThreads), 0, s, a);
+void col_inv(int maxt, const ColArgs<T>& a, dim3 g, hipStream_t s) {
+  if (maxt <= 1) hipLaunchKernelGGL((k_col<T, N, 1, 1>), g, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_col<T, N, 1, kMaxTerms>), g, dim3(kThreads), 0, s, a);
 }
 template <typename T, int N>
 void col_fwd(const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((k_col<T, N, -1>), g, dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_col<T, N, -1, 1>), g, dim3(kThreads), 0, s, a);
+}
+template <typename T, int N>
+int col_occupancy(int dir, int maxt) {
+  int blocks = 0;
+  hipError_t e;
+  if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, -1, 1>, kThreads, 0);
+  else if (maxt <= 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, 1>, kThreads, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, kMaxTerms>, kThreads, 0);
+  return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 template <typename T, int N>
 void rhs(const RhsArgs<T>& a, dim3 g, hipStream_t s) {
@@ -63,6 +73,7 @@ Kern<T> make() {
   k.rhs = rhs<T, N>;
   k.row = row<T, N>;
   k.row_occupancy = row_occupancy<T, N>;
+  k.col_occupancy = col_occupancy<T, N>;
   return k;
 }
 

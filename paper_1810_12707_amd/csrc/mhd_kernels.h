@@ -27,8 +27,7 @@ template <int N> struct Band {
 template <int N> __device__ __forceinline__ int band_pos(int l) { return l <= Band<N>::K ? l : l + N - Band<N>::NB; }
 template <int N> __device__ __forceinline__ int band_k(int l) { return l <= Band<N>::K ? l : l - Band<N>::NB; }
 
-// Column tile width: 16 columns while the LDS tile stays within 32 KiB (four
-// workgroups per CU), else 8.
+// Column tile width: 16 columns while the LDS tile stays within 32 KiB, else 8.
 template <typename T, int N> constexpr int col_width() {
   constexpr int bytes = N * 2 * (int)sizeof(T);
   return 32768 / bytes >= 16 ? 16 : 8;
@@ -90,25 +89,26 @@ __device__ __forceinline__ TileField tile_field(int nfields) {
 
 // ------------------------------------------------------------------ k_col
 // S = +1: inverse pass, band (nb) in -> N out.  S = -1: forward, N in -> band out.
-// Flat grid over (outer, tile, field); see tile_field.  The first FFT pass
-// loads straight from global memory (skipping the zero gap of a band input);
-// the last pass stores straight to global memory (skipping dropped modes).
-template <typename T, int N, int S>
+// Persistent: items (outer, tile, field), field fastest, walked in XCD-blocked
+// order (xcd_item), so the outputs of one tile -- which share inputs -- run
+// together on one XCD.  The first FFT pass reads its inputs from registers
+// that were loaded from HBM while the previous item was being transformed
+// (up to MAXT input terms per element; the zero gap of a band input is never
+// loaded); the last pass stores straight to HBM (dropped modes skipped).
+template <typename T, int N, int S, int MAXT>
 __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   constexpr int C = col_width<T, N>();
   constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
+  using FP = FirstPass<N, C, kThreads>;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
-  const TileField tf = tile_field(a.nout);
-  const int f = tf.field;
   const bool zpass = (a.kind == PK_ZINV || a.kind == PK_ZFWD);
   // z passes: columns are (ky, kx) flattened over the padded pitch; padding
   // columns (kx >= NH) are never read or written
   const int ncols = zpass ? NBB * NHP : NH;
   const int ntiles = (ncols + C - 1) / C;
-  const int outer = tf.tile / ntiles;
-  const int c0 = (tf.tile - outer * ntiles) * C;
+  const int total = ntiles * (zpass ? 1 : N) * a.nout;  // < 2^31 for every supported size
   // strides (complex elements) of the input and output layouts
   int64_t os_in, ls_in, os_out, ls_out;
   switch (a.kind) {
@@ -118,70 +118,115 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
     default: os_in = 0; ls_in = NBB * NHP; os_out = 0; ls_out = NBB * NHP; break;
   }
   load_twiddles<T, N>(stw, a.tw, tid);
-  const OutSpec& sp = a.spec[f];
-  const int nt = sp.nterms;
-  const T* p0 = a.in[sp.t[0].src];
-  const T* p1 = nt > 1 ? a.in[sp.t[1].src] : p0;
-  const T* p2 = nt > 2 ? a.in[sp.t[2].src] : p0;
-  const T* const* in = a.in;
-  (void)in;
-  const int64_t base_in = outer * os_in + c0;
-  auto col_ok = [&](int col) {
-    return col < ncols && (!zpass || col - (col / NHP) * NHP < NH);
+  auto col_ok = [&](int col) { return col < ncols && (!zpass || col - (col / NHP) * NHP < NH); };
+
+  struct Item {
+    int f, outer, c0;
   };
-  auto load = [&](int c, int q) -> cx<T> {
-    const int col = c0 + c;
-    cx<T> v = mk<T>(0, 0);
-    if (!col_ok(col)) return v;
-    int l = q;
-    if constexpr (S > 0) {
-      l = pos_band<N>(q);
-      if (l < 0) return v;
-    }
-    const int64_t idx = base_in + l * ls_in + c;
-    int kx, ky = 0, kz = 0;
-    if (zpass) {
-      ky = band_k<N>(col / NHP);
-      kx = col - (col / NHP) * NHP;
-      if (S > 0) kz = band_k<N>(l);
-    } else {
-      kx = col;
-      if (S > 0) ky = band_k<N>(l);
-    }
-    const cx<T> x0 = ld(p0, idx);
-    const cx<T> x1 = nt > 1 ? ld(p1, idx) : mk<T>(0, 0);
-    const cx<T> x2 = nt > 2 ? ld(p2, idx) : mk<T>(0, 0);
-    const cx<T> xs[3] = {x0, x1, x2};
+  auto decode = [&](int item) {
+    Item it;
+    const int t = item / a.nout;
+    it.f = item - t * a.nout;
+    it.outer = t / ntiles;
+    it.c0 = (t - it.outer * ntiles) * C;
+    return it;
+  };
+  // raw first-pass loads of one item, one set per input term
+  cx<T> px[MAXT][FP::CNT][FP::R];
+  auto issue = [&](const Item& it) {
+    const OutSpec& sp = a.spec[it.f];
+    const int64_t base_in = it.outer * os_in + it.c0;
 #pragma unroll
-    for (int t = 0; t < kMaxTerms; ++t) {
-      if (t < nt) {
-        const Term& tm = sp.t[t];
-        const T cf = T(tm.coef);
-        const cx<T> xv = xs[t];
-        if (tm.axis < 0) {
-          v.x += cf * xv.x;
-          v.y += cf * xv.y;
-        } else {
-          const T ck = cf * T(tm.axis == 0 ? kx : (tm.axis == 1 ? ky : kz));
-          v.x -= ck * xv.y;
-          v.y += ck * xv.x;
+    for (int i = 0; i < FP::CNT; ++i) {
+      const int w = tid + i * kThreads;
+      int c, j;
+      lane_map<C, FP::NBF, 0>(w, c, j);
+      const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && col_ok(it.c0 + c);
+#pragma unroll
+      for (int r = 0; r < FP::R; ++r) {
+        const int q = j + r * FP::NBF;
+        const int l = S > 0 ? pos_band<N>(q) : q;
+        if (ok && l >= 0) {
+          const int64_t idx = base_in + l * ls_in + c;
+#pragma unroll
+          for (int t = 0; t < MAXT; ++t)
+            if (t < sp.nterms) px[t][i][r] = ld(a.in[sp.t[t].src], idx);
         }
       }
     }
-    return v;
   };
-  T* out = a.out[f];
-  const int64_t base_out = outer * os_out + c0;
-  auto store = [&](int, int, int c, int q, cx<T> v) {
-    if (!col_ok(c0 + c)) return;
-    int l = q;
-    if constexpr (S < 0) {
-      l = pos_band<N>(q);
-      if (l < 0) return;
+
+  const int G = gridDim.x;
+  int item = (int)xcd_item(blockIdx.x, G, 0, total);
+  if (item >= 0) issue(decode(item));
+  for (int k = 0; item >= 0; ++k) {
+    const Item it = decode(item);
+    const OutSpec& sp = a.spec[it.f];
+    // combine the prefetched terms with their spectral multipliers
+    cx<T> v[FP::CNT][FP::R];
+#pragma unroll
+    for (int i = 0; i < FP::CNT; ++i) {
+      const int w = tid + i * kThreads;
+      int c, j;
+      lane_map<C, FP::NBF, 0>(w, c, j);
+      const int col = it.c0 + c;
+      const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && col_ok(col);
+      int kx, ky = 0;
+      if (zpass) {
+        ky = band_k<N>(col / NHP);
+        kx = col - (col / NHP) * NHP;
+      } else {
+        kx = col;
+      }
+#pragma unroll
+      for (int r = 0; r < FP::R; ++r) {
+        const int q = j + r * FP::NBF;
+        const int l = S > 0 ? pos_band<N>(q) : q;
+        cx<T> acc = mk<T>(0, 0);
+        if (ok && l >= 0) {
+          int kyy = ky, kz = 0;
+          if (S > 0) {
+            if (zpass) kz = band_k<N>(l);
+            else kyy = band_k<N>(l);
+          }
+#pragma unroll
+          for (int t = 0; t < MAXT; ++t) {
+            if (t < sp.nterms) {
+              const Term& tm = sp.t[t];
+              const T cf = T(tm.coef);
+              const cx<T> xv = px[t][i][r];
+              if (tm.axis < 0) {
+                acc.x += cf * xv.x;
+                acc.y += cf * xv.y;
+              } else {
+                const T ck = cf * T(tm.axis == 0 ? kx : (tm.axis == 1 ? kyy : kz));
+                acc.x -= ck * xv.y;
+                acc.y += ck * xv.x;
+              }
+            }
+          }
+        }
+        v[i][r] = acc;
+      }
     }
-    st(out, base_out + l * ls_out + c, v);
-  };
-  fft_reg<T, N, C, kThreads, C, 1, S>(tile, stw, tid, C, load, store);
+    __syncthreads();  // the previous item's last pass is done reading the tile
+    T* out = a.out[it.f];
+    const int64_t base_out = it.outer * os_out + it.c0;
+    auto store = [&](int, int, int c, int q, cx<T> val) {
+      if (!col_ok(it.c0 + c)) return;
+      int l = q;
+      if constexpr (S < 0) {
+        l = pos_band<N>(q);
+        if (l < 0) return;
+      }
+      st(out, base_out + l * ls_out + c, val);
+    };
+    fft_first_regs<T, N, C, kThreads, C, 1, S, 0, 0>(tile, v, tid, C, store);
+    const int next = (int)xcd_item(blockIdx.x, G, k + 1, total);
+    if (next >= 0) issue(decode(next));  // in flight during this item's LDS passes
+    fft_rest<T, N, C, kThreads, C, 1, S, 0, 0>(tile, stw, tid, C, store);
+    item = next;
+  }
 }
 
 // ------------------------------------------------------------------ k_zfwd_rhs

@@ -10,8 +10,10 @@ template <typename T>
 struct Kern {
   int n = 0;
   int col_width = 0;  // columns per workgroup of the column passes
-  void (*col_inv)(const ColArgs<T>&, dim3, hipStream_t) = nullptr;
+  // column passes; maxt = largest number of terms of any output spec (1 or 3)
+  void (*col_inv)(int maxt, const ColArgs<T>&, dim3, hipStream_t) = nullptr;
   void (*col_fwd)(const ColArgs<T>&, dim3, hipStream_t) = nullptr;
+  int (*col_occupancy)(int dir, int maxt) = nullptr;
   void (*rhs)(const RhsArgs<T>&, dim3, hipStream_t) = nullptr;
   void (*row)(int mode, const RowArgs<T>&, dim3, hipStream_t) = nullptr;
   // resident workgroups per CU of a row-pass mode (persistent grid sizing)
