@@ -72,17 +72,21 @@ def describe(case) -> str:
             f"gamma=5/3, nu=eta={case.nu:g}, dt={case.dt:.3e} (CFL 0.1), AB2, 2/3 dealiasing")
 
 
-def run_gpu(case, steps: int, warmup: int, diag_every: int = 10, with_fp64_error: bool = True):
-    import numpy as np
+FIELDS = ("rho", "m_x", "m_y", "m_z", "B_x", "B_y", "B_z", "E")
+
+
+def timed_run(case, precision: str, steps: int, warmup: int, diag_every: int = 10):
+    """warmup + timed steps of one precision; returns timings, profile and the
+    final state (FP64 host copy is not made: the state stays on the GPU)."""
     import torch
 
     from paper_1810_12707_amd.mhd import Solver
 
-    n = case.n
     dev = torch.device("cuda:0")
     U64 = torch.from_numpy(case.U).to(dev)
-    S = Solver(n, precision="fp32", gamma=case.gamma, nu=case.nu, eta=case.eta, dt=case.dt, device=dev)
+    S = Solver(case.n, precision=precision, gamma=case.gamma, nu=case.nu, eta=case.eta, dt=case.dt, device=dev)
     S.set_state(U64)
+    del U64
     for _ in range(warmup):
         S.step(1)
     torch.cuda.synchronize()
@@ -105,30 +109,61 @@ def run_gpu(case, steps: int, warmup: int, diag_every: int = 10, with_fp64_error
     prof = S.profile_read()
     S.profile(False)
     rc_end, diag = S.diagnostics()
-    step_bytes = S.step_bytes
-    ws_bytes = S.workspace.numel()
-    err = None
-    if with_fp64_error:
-        # same start, same number of steps, FP64 path on the GPU
-        Uf32 = S.get_state(torch.float64)
-        S.close()
-        del S
-        torch.cuda.empty_cache()
-        D = Solver(n, precision="fp64", gamma=case.gamma, nu=case.nu, eta=case.eta, dt=case.dt, device=dev)
-        D.set_state(U64)
-        D.step(warmup + steps)
-        Uf64 = D.get_state(torch.float64)
-        err = {name: float(torch.linalg.vector_norm(Uf32[f] - Uf64[f]) / torch.linalg.vector_norm(Uf64[f]))
-               for f, name in enumerate(("rho", "m_x", "m_y", "m_z", "B_x", "B_y", "B_z", "E"))}
-        D.close()
-        del D, Uf32, Uf64
-    else:
-        S.close()
-        del S
-    del U64
+    out = {"ms": ms, "wall_s": wall, "prof": prof, "diag": diag, "rc": (rc_diag, rc_end),
+           "step_bytes": S.step_bytes, "ws_bytes": S.workspace.numel(), "state": S.get_state(torch.float64)}
+    S.close()
+    del S
     torch.cuda.empty_cache()
-    return {"ms": ms, "wall_s": wall, "prof": prof, "diag": diag, "rc": (rc_diag, rc_end), "step_bytes": step_bytes,
-            "ws_bytes": ws_bytes, "err_vs_fp64": err}
+    return out
+
+
+def fp64_state(case, nsteps: int):
+    """The FP64 GPU run of the same start, same number of steps."""
+    import torch
+
+    from paper_1810_12707_amd.mhd import Solver
+
+    dev = torch.device("cuda:0")
+    D = Solver(case.n, precision="fp64", gamma=case.gamma, nu=case.nu, eta=case.eta, dt=case.dt, device=dev)
+    D.set_state(torch.from_numpy(case.U).to(dev))
+    D.step(nsteps)
+    st = D.get_state(torch.float64)
+    D.close()
+    del D
+    torch.cuda.empty_cache()
+    return st
+
+
+def rel_errors(a, ref):
+    import torch
+
+    return {name: float(torch.linalg.vector_norm(a[f] - ref[f]) / torch.linalg.vector_norm(ref[f]))
+            for f, name in enumerate(FIELDS)}
+
+
+def run_gpu(case, steps: int, warmup: int, with_fp64_error: bool = True, with_mixed: bool = True):
+    r = timed_run(case, "fp32", steps, warmup)
+    mixed = timed_run(case, "mixed", steps, warmup) if with_mixed else None
+    ref = fp64_state(case, warmup + steps) if with_fp64_error else None
+    r["err_vs_fp64"] = rel_errors(r["state"], ref) if ref is not None else None
+    if mixed is not None:
+        mixed["err_vs_fp64"] = rel_errors(mixed["state"], ref) if ref is not None else None
+        del mixed["state"]
+    del r["state"], ref
+    r["mixed"] = mixed
+    return r
+
+
+def mixed_line(m, n, steps):
+    if m is None:
+        return None
+    sec = m["ms"] * 1e-3
+    return {"value": round(n ** 3 * steps / sec, 1), "unit": "grid-point-steps/s",
+            "ms_per_step": round(m["ms"] / steps, 5), "err_vs_fp64": m["err_vs_fp64"], "status": m["rc"],
+            "step_hbm": {"GBps": round(m["step_bytes"] / (sec / steps) / 1e9, 1),
+                         "frac": round(m["step_bytes"] / (sec / steps) / 1e9 / HBM_PEAK_GBS, 4)},
+            "passes": pass_table(m["prof"], steps),
+            "what": "FP32 data; radix-16 FFT stages as split-BF16x3 MFMA products, FP32 accumulate"}
 
 
 def roofline_from(prof: dict, traffic: dict | None):
@@ -203,6 +238,7 @@ def main(argv=None):
     ap.add_argument("--secondary-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-error", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -219,7 +255,7 @@ def main(argv=None):
     log(f"[bench] building input {a.config}")
     case = make_case(a.config)
     log(f"[bench] n={case.n} dt={case.dt:.3e}; warmup {a.warmup}, timed {a.steps} steps")
-    r = run_gpu(case, a.steps, a.warmup, with_fp64_error=not a.no_fp64_error)
+    r = run_gpu(case, a.steps, a.warmup, with_fp64_error=not a.no_fp64_error, with_mixed=not a.no_mixed)
     n = case.n
     sec = r["ms"] * 1e-3
     value = n ** 3 * a.steps / sec
@@ -233,7 +269,7 @@ def main(argv=None):
     if a.secondary:
         log(f"[bench] secondary workload {a.secondary}")
         c2 = make_case(a.secondary)
-        r2 = run_gpu(c2, a.secondary_steps, 3, with_fp64_error=not a.no_fp64_error)
+        r2 = run_gpu(c2, a.secondary_steps, 3, with_fp64_error=not a.no_fp64_error, with_mixed=not a.no_mixed)
         s2 = r2["ms"] * 1e-3
         dom2, roof2 = roofline_from(r2["prof"], load_traffic(c2.n))
         secondary = {
@@ -245,6 +281,7 @@ def main(argv=None):
                          "frac": round(r2["step_bytes"] / (s2 / a.secondary_steps) / 1e9 / HBM_PEAK_GBS, 4)},
             "passes": pass_table(r2["prof"], a.secondary_steps),
             "err_vs_fp64": r2["err_vs_fp64"], "status": r2["rc"],
+            "mixed_path": mixed_line(r2["mixed"], c2.n, a.secondary_steps),
         }
         log(f"[bench] secondary {secondary['ms_per_step']} ms/step")
         del c2
@@ -276,7 +313,7 @@ def main(argv=None):
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "passes": pass_table(r["prof"], a.steps),
         "err_vs_fp64": r["err_vs_fp64"],
-        "mixed_path": None,
+        "mixed_path": mixed_line(r["mixed"], n, a.steps),
         "status": r["rc"],
         "wall_s": round(r["wall_s"], 4),
         "secondary": secondary,

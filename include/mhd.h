@@ -36,7 +36,7 @@
  *  - One context per stream; a context is not thread-safe.
  *
  * Supported sizes: n in {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384,
- * 512} for MHD_FP64 and additionally 768 and 1024 for MHD_FP32
+ * 512} for MHD_FP64 and additionally 768 and 1024 for MHD_FP32 and MHD_MIXED
  * (mhd_supported_size).
  */
 #ifndef MHD_H
@@ -60,8 +60,14 @@ enum {
     MHD_E_STATE = -7      /* no state has been set yet */
 };
 
-/* Working precision (mhd_params.precision) and real-field element types. */
-enum { MHD_FP64 = 0, MHD_FP32 = 1 };
+/* Working precision (mhd_params.precision) and real-field element types
+ * (dtype arguments take MHD_FP64 or MHD_FP32 only).  MHD_MIXED stores and
+ * computes in FP32 but runs every radix-16 FFT stage that goes LDS to LDS as
+ * a matrix product on the MFMA units: the DFT matrix and the data are split
+ * into BF16 high and low parts and three products are accumulated in FP32
+ * (the low*low product is dropped); twiddles stay FP32.  Real fields and
+ * compact spectra of an MHD_MIXED context are FP32. */
+enum { MHD_FP64 = 0, MHD_FP32 = 1, MHD_MIXED = 2 };
 
 /* mhd_params.flags */
 enum {
@@ -70,7 +76,7 @@ enum {
 
 typedef struct {
     int32_t n;         /* grid points per side */
-    int32_t precision; /* MHD_FP64 or MHD_FP32 */
+    int32_t precision; /* MHD_FP64, MHD_FP32 or MHD_MIXED */
     int32_t flags;     /* MHD_FLAG_* */
     int32_t reserved;  /* must be 0 */
     double gamma;      /* ratio of specific heats, > 1 */

@@ -1,12 +1,21 @@
 // Batched in-LDS FFTs for gfx950.
 //
 // A workgroup holds NB sequences of length N in LDS, element (b, l) at
-// buf[b*BS + l*ES].  Each radix-R pass of the Stockham autosort (decimation
-// in time) lets every thread read R elements of one butterfly into registers,
-// twiddle them, do an R-point DFT in registers, and, after a barrier, write
-// them to their sorted positions; the output ends in natural order, so no
-// bit-reversal pass is needed.  Butterflies are assigned batch-fastest across
-// lanes so that a column tile (ES = C, BS = 1) gives unit-stride LDS access.
+// lds_at(b, l).  Each radix-R pass of the Stockham autosort (decimation in
+// time) lets every thread read R elements of one butterfly into registers,
+// twiddle them, do an R-point DFT, and, after a barrier, write them to their
+// sorted positions; the output ends in natural order, so no bit-reversal pass
+// is needed.  Lanes are assigned to butterflies batch-fastest (column tiles,
+// unit-stride LDS access across adjacent columns) or butterfly-fastest (rows).
+//
+// A plan (PlanT) is the list of radices.  In a mixed-precision plan
+// (MX = true) every radix-16 pass that runs LDS to LDS is a matrix product on
+// the MFMA units: the 16-point DFT of 16 butterflies at once is the real
+// 32 x 32 matrix [[Re W, -Im W], [Im W, Re W]] times the 32 x 16 matrix of their
+// (Re, Im) inputs; W and the inputs are each split into BF16 high and low parts
+// (hi = RNE(x), lo = RNE(x - hi)) and Y = W_hi X_hi + W_hi X_lo + W_lo X_hi is
+// accumulated in FP32 by v_mfma_f32_16x16x32_bf16 (the lo*lo term, about 2^-16
+// relative, is dropped).  Twiddles stay FP32 on the VALU.
 //
 // Twiddles come from a table of exp(-2 pi i j / N), j < N, computed in FP64
 // on the host and rounded once to T; the inverse uses the conjugates.
@@ -38,6 +47,13 @@ template <typename X> __device__ __forceinline__ X ctimes_i(X a) { X r; r.x = -a
 template <typename X> __device__ __forceinline__ X ctimes_mi(X a) { X r; r.x = a.y; r.y = -a.x; return r; }
 // multiply by i^s: sign s = -1 gives -i (forward), +1 gives +i (inverse)
 template <int S, typename X> __device__ __forceinline__ X ctimes_si(X a) { return S < 0 ? ctimes_mi(a) : ctimes_i(a); }
+
+// cos(2 pi m / 16), m = 0..15 (sin(2 pi m/16) = cos(2 pi (m - 4)/16))
+__device__ constexpr double kCos16[16] = {
+    1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+    0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+    -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+    0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
 
 // ---------------------------------------------------------------- small DFTs
 // In place, natural order in and out; S = -1 forward, +1 inverse.
@@ -93,22 +109,56 @@ template <int S, typename X> __device__ __forceinline__ void dft8(X* v) {
   }
 }
 
+// 16 = 4 x 4: inner 4-point DFTs over stride-4 samples, twiddles
+// exp(S 2 pi i n2 k1 / 16), outer 4-point DFTs; output index k1 + 4 k2.
+template <int S, typename X> __device__ __forceinline__ void dft16(X* v) {
+  using T = decltype(v[0].x);
+  X b[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    X a[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+    dft4<S>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      const int m = (n2 * k1) & 15;
+      X w;
+      w.x = T(kCos16[m]);
+      w.y = T(S) * T(kCos16[(m + 12) & 15]);
+      b[n2][k1] = (m == 0) ? a[k1] : cmul(a[k1], w);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    X c[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+    dft4<S>(c);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = c[k2];
+  }
+}
+
 template <int R, int S, typename X> __device__ __forceinline__ void dft(X* v) {
   if constexpr (R == 2) dft2<S>(v);
   else if constexpr (R == 3) dft3<S>(v);
   else if constexpr (R == 4) dft4<S>(v);
   else if constexpr (R == 8) dft8<S>(v);
-  else static_assert(R == 2 || R == 3 || R == 4 || R == 8, "unsupported radix");
+  else if constexpr (R == 16) dft16<S>(v);
+  else static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "unsupported radix");
 }
 
 // ---------------------------------------------------------------- radix plans
 
-template <int N> struct Plan;
-#define MHD_PLAN(NN, ...)                                              \
-  template <> struct Plan<NN> {                                        \
-    static constexpr int r[] = {__VA_ARGS__};                          \
-    static constexpr int np = sizeof(r) / sizeof(int);                 \
-  };
+template <int NN, bool MXX, int... Rs> struct PlanT {
+  static constexpr int N = NN;
+  static constexpr bool MX = MXX;  // radix-16 LDS passes on MFMA (split BF16 x 3)
+  static constexpr int r[] = {Rs...};
+  static constexpr int np = sizeof...(Rs);
+};
+
+// FP32 / FP64 plans (VALU only) and mixed plans (radix-16 stages after the
+// first pass, which reads from global memory and stays on the VALU).
+template <int N, bool MX> struct PlanSel;
+#define MHD_PLAN(NN, ...) template <> struct PlanSel<NN, false> { using type = PlanT<NN, false, __VA_ARGS__>; };
+#define MHD_PLAN_MX(NN, ...) template <> struct PlanSel<NN, true> { using type = PlanT<NN, true, __VA_ARGS__>; };
 MHD_PLAN(8, 8)
 MHD_PLAN(12, 4, 3)
 MHD_PLAN(16, 4, 4)
@@ -124,18 +174,35 @@ MHD_PLAN(384, 8, 4, 4, 3)
 MHD_PLAN(512, 8, 8, 8)
 MHD_PLAN(768, 8, 8, 4, 3)
 MHD_PLAN(1024, 8, 8, 4, 4)
+MHD_PLAN_MX(8, 8)
+MHD_PLAN_MX(12, 4, 3)
+MHD_PLAN_MX(16, 4, 4)
+MHD_PLAN_MX(24, 8, 3)
+MHD_PLAN_MX(32, 2, 16)
+MHD_PLAN_MX(48, 3, 16)
+MHD_PLAN_MX(64, 4, 16)
+MHD_PLAN_MX(96, 2, 3, 16)
+MHD_PLAN_MX(128, 8, 16)
+MHD_PLAN_MX(192, 4, 3, 16)
+MHD_PLAN_MX(256, 16, 16)
+MHD_PLAN_MX(384, 3, 8, 16)
+MHD_PLAN_MX(512, 2, 16, 16)
+MHD_PLAN_MX(768, 3, 16, 16)
+MHD_PLAN_MX(1024, 4, 16, 16)
 #undef MHD_PLAN
+#undef MHD_PLAN_MX
+template <int N, bool MX = false> using PlanOf = typename PlanSel<N, MX>::type;
 
-template <int N> constexpr int plan_ns(int p) {
+template <class PL> constexpr int plan_ns(int p) {
   int ns = 1;
-  for (int i = 0; i < p; ++i) ns *= Plan<N>::r[i];
+  for (int i = 0; i < p; ++i) ns *= PL::r[i];
   return ns;
 }
 
-template <int N> constexpr bool plan_ok() {
+template <class PL> constexpr bool plan_ok() {
   int prod = 1;
-  for (int i = 0; i < Plan<N>::np; ++i) prod *= Plan<N>::r[i];
-  return prod == N;
+  for (int i = 0; i < PL::np; ++i) prod *= PL::r[i];
+  return prod == PL::N;
 }
 
 // Lane -> (sequence b, butterfly j) assignment of a pass with NBF butterflies
@@ -162,11 +229,12 @@ __device__ __forceinline__ int lds_at(int b, int pos) {
   else return b * BS + pos * ES;
 }
 
-// One Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0, int PADSH = 0>
-__device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
-  constexpr int R = Plan<N>::r[P];
-  constexpr int NS = plan_ns<N>(P);
+// One VALU Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0, int PADSH = 0>
+__device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
+  constexpr int N = PL::N;
+  constexpr int R = PL::r[P];
+  constexpr int NS = plan_ns<PL>(P);
   constexpr int NBF = N / R;
   constexpr int TOT = NB * NBF;
   constexpr int CNT = (TOT + NT - 1) / NT;
@@ -206,29 +274,149 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
   __syncthreads();
 }
 
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, int P = 0>
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// A-operand halves of the 16-point DFT as a real 32 x 32 matrix for this lane
+// (row q = lane mod 16; k-range 8 (lane / 16) .. +8 of the (Re x, Im x) inputs):
+// block 0 gives Re y_q, block 1 Im y_q.
+template <int S>
+__device__ __forceinline__ void dft16_operands(int lane, bf16x8& a0h, bf16x8& a0l, bf16x8& a1h, bf16x8& a1l) {
+  const int q = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int r = (8 * g + t) & 15;  // input index
+    const bool im_in = g >= 2;       // column block of Im x
+    const int m = (q * r) & 15;
+    const float re = float(kCos16[m]);
+    const float im = float(S) * float(kCos16[(m + 12) & 15]);
+    const float w0 = im_in ? -im : re;  // Re y: Re W Re x - Im W Im x
+    const float w1 = im_in ? re : im;   // Im y: Im W Re x + Re W Im x
+    const __bf16 h0 = (__bf16)w0, h1 = (__bf16)w1;
+    a0h[t] = h0;
+    a0l[t] = (__bf16)(w0 - (float)h0);
+    a1h[t] = h1;
+    a1l[t] = (__bf16)(w1 - (float)h1);
+  }
+}
+
+// Radix-16 Stockham pass on the MFMA units (FP32 data, split BF16 x 3).  Each
+// wave takes 16 butterflies at a time: lane (n = lane mod 16, g = lane / 16)
+// reads elements 8 (g mod 2) .. +8 of butterfly n, twiddles them in FP32 and
+// keeps their real (g < 2) or imaginary (g >= 2) parts as the B operand; after
+// the products lane (n, g) holds outputs q = 4g .. 4g+3 of butterfly n.
+template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH>
+__device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int tid, int b_act) {
+  constexpr int N = PL::N;
+  constexpr int R = 16;
+  constexpr int NS = plan_ns<PL>(P);
+  constexpr int NBF = N / R;
+  constexpr int TOT = NB * NBF;
+  constexpr int NGRP = (TOT + 15) / 16;
+  constexpr int NW = NT / 64;
+  constexpr int GPW = (NGRP + NW - 1) / NW;  // groups per wave
+  const int lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  bf16x8 a0h, a0l, a1h, a1l;
+  dft16_operands<S>(lane, a0h, a0l, a1h, a1l);
+  floatx4 yr[GPW], yi[GPW];
+#pragma unroll
+  for (int s = 0; s < GPW; ++s) {
+    const int grp = wv + s * NW;
+    const int w = grp * 16 + n;
+    int b, j;
+    lane_map<NB, NBF, MAP>(w, b, j);
+    const bool ok = grp < NGRP && w < TOT && b < b_act;
+    const int k = j % NS;
+    bf16x8 xh, xl;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = 8 * (g & 1) + t;
+      float2 x = ok ? buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)] : make_float2(0.f, 0.f);
+      if constexpr (NS > 1) {
+        if (r > 0) {
+          const float2 tv = tw[k * r * (N / (NS * R))];
+          x = (S < 0) ? cmul(x, tv) : cmulc(x, tv);
+        }
+      }
+      const float val = g < 2 ? x.x : x.y;
+      const __bf16 h = (__bf16)val;
+      xh[t] = h;
+      xl[t] = (__bf16)(val - (float)h);
+    }
+    floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, xh, c0, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, xl, c0, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, xh, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, xh, c1, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, xl, c1, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1l, xh, c1, 0, 0, 0);
+    yr[s] = c0;
+    yi[s] = c1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < GPW; ++s) {
+    const int grp = wv + s * NW;
+    const int w = grp * 16 + n;
+    int b, j;
+    lane_map<NB, NBF, MAP>(w, b, j);
+    if (grp < NGRP && w < TOT && b < b_act) {
+      const int k = j % NS;
+      const int d = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int q = 4 * g + t;
+        buf[lds_at<ES, BS, PADSH>(b, d + q * NS)] = make_float2(yr[s][t], yi[s][t]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0, int PADSH = 0>
+__device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
+  if constexpr (PL::MX && PL::r[P] == 16) {
+    static_assert(sizeof(T) == 4, "the mixed path works on FP32 data");
+    fft_pass_mfma<PL, NB, NT, ES, BS, S, P, MAP, PADSH>(reinterpret_cast<float2*>(buf),
+                                                        reinterpret_cast<const float2*>(tw), tid, b_act);
+  } else {
+    fft_pass_valu<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
+  }
+}
+
+// All passes LDS to LDS.
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, int P = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
-  static_assert(plan_ok<N>(), "radix plan does not multiply to N");
-  if constexpr (P < Plan<N>::np) {
-    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
-    lds_fft<T, N, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
+  static_assert(plan_ok<PL>(), "radix plan does not multiply to N");
+  if constexpr (P < PL::np) {
+    fft_pass<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
+    lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
   }
 }
 
 // Passes 1 .. np-2 of a plan, LDS to LDS.
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, int P>
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, int P>
 __device__ __forceinline__ void fft_mid_passes(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
-  if constexpr (P < Plan<N>::np - 1) {
-    fft_pass<T, N, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
-    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
+  if constexpr (P < PL::np - 1) {
+    fft_pass<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
+    fft_mid_passes<T, PL, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
   }
 }
 
-// Shape of the first pass of a plan: R0 elements per butterfly, CNT0
+// Shape of the first pass of a plan: R elements per butterfly, CNT
 // butterflies per thread.
-template <int N, int NB, int NT> struct FirstPass {
-  static constexpr int R = Plan<N>::r[0];
-  static constexpr int NBF = N / R;
+template <class PL, int NB, int NT> struct FirstPass {
+  static constexpr int R = PL::r[0];
+  static constexpr int NBF = PL::N / R;
+  static constexpr int TOT = NB * NBF;
+  static constexpr int CNT = (TOT + NT - 1) / NT;
+};
+
+// Per-thread shape of the last pass (outputs handed to store(i, r, ...)).
+template <class PL, int NB, int NT> struct LastPass {
+  static constexpr int R = PL::r[PL::np - 1];
+  static constexpr int NBF = PL::N / R;
   static constexpr int TOT = NB * NBF;
   static constexpr int CNT = (TOT + NT - 1) / NT;
 };
@@ -237,11 +425,11 @@ template <int N, int NB, int NT> struct FirstPass {
 // sequence b for this thread's i-th butterfly): R-point DFTs, then either the
 // final outputs (one-pass plans) or the LDS writes of the next pass, followed
 // by a barrier.
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
-__device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<N, NB, NT>::CNT][Plan<N>::r[0]],
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
+__device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<PL, NB, NT>::CNT][PL::r[0]],
                                                int tid, int b_act, Store&& store) {
-  using FP = FirstPass<N, NB, NT>;
-  constexpr int NP = Plan<N>::np;
+  using FP = FirstPass<PL, NB, NT>;
+  constexpr int NP = PL::np;
 #pragma unroll
   for (int i = 0; i < FP::CNT; ++i) {
     const int w = tid + i * NT;
@@ -261,35 +449,52 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
   if constexpr (NP > 1) __syncthreads();
 }
 
-// Middle passes (LDS to LDS) and the last pass (LDS to store()).
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
+// Middle passes (LDS to LDS) and the last pass, whose outputs go to
+// store(i, r, b, pos, value) with pos = j + r N/R for the thread's i-th
+// butterfly j.  On the VALU the last pass computes straight into registers;
+// an MFMA last pass writes LDS and the same (i, r, pos) are then read back.
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
 __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Store&& store) {
-  constexpr int NP = Plan<N>::np;
+  constexpr int NP = PL::np;
   if constexpr (NP > 1) {
-    fft_mid_passes<T, N, NB, NT, ES, BS, S, MAP, PADSH, 1>(buf, tw, tid, b_act);
-    constexpr int PL = NP - 1;
-    constexpr int R = Plan<N>::r[PL];
-    constexpr int NS = plan_ns<N>(PL);  // = N / R
-    constexpr int NBF = N / R;
+    fft_mid_passes<T, PL, NB, NT, ES, BS, S, MAP, PADSH, 1>(buf, tw, tid, b_act);
+    constexpr int PLAST = NP - 1;
+    constexpr int R = PL::r[PLAST];
+    constexpr int NS = plan_ns<PL>(PLAST);  // = N / R
+    constexpr int NBF = PL::N / R;
     constexpr int TOT = NB * NBF;
     constexpr int CNT = (TOT + NT - 1) / NT;
+    if constexpr (PL::MX && R == 16) {
+      fft_pass<T, PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH>(buf, tw, tid, b_act);
 #pragma unroll
-    for (int i = 0; i < CNT; ++i) {
-      const int w = tid + i * NT;
-      int b, j;
-      lane_map<NB, NBF, MAP>(w, b, j);
-      if ((TOT % NT == 0 || w < TOT) && b < b_act) {
-        cx<T> v[R];
+      for (int i = 0; i < CNT; ++i) {
+        const int w = tid + i * NT;
+        int b, j;
+        lane_map<NB, NBF, MAP>(w, b, j);
+        if ((TOT % NT == 0 || w < TOT) && b < b_act) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cx<T> t = tw[j * r];  // k = j mod NS = j; index k r N/(NS R) = j r
-          v[r] = (S < 0) ? cmul(v[r], t) : cmulc(v[r], t);
+          for (int r = 0; r < R; ++r) store(i, r, b, j + r * NS, buf[lds_at<ES, BS, PADSH>(b, j + r * NS)]);
         }
-        dft<R, S>(v);
+      }
+    } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) store(i, r, b, j + r * NS, v[r]);
+      for (int i = 0; i < CNT; ++i) {
+        const int w = tid + i * NT;
+        int b, j;
+        lane_map<NB, NBF, MAP>(w, b, j);
+        if ((TOT % NT == 0 || w < TOT) && b < b_act) {
+          cx<T> v[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const cx<T> t = tw[j * r];  // k = j mod NS = j; index k r N/(NS R) = j r
+            v[r] = (S < 0) ? cmul(v[r], t) : cmulc(v[r], t);
+          }
+          dft<R, S>(v);
+#pragma unroll
+          for (int r = 0; r < R; ++r) store(i, r, b, j + r * NS, v[r]);
+        }
       }
     }
   }
@@ -297,17 +502,17 @@ __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, i
 
 // Register-ended FFT: the first pass takes its inputs from load(b, pos)
 // (global memory) and the last pass hands its outputs to
-// store(i, r, b, pos, value) from registers; only the passes in between go
-// through LDS.  load() is called for all CNT*R elements of a thread before any
-// arithmetic, so their memory requests are in flight together.  For one-pass
-// plans the inputs go straight from load() through the DFT to store().
-// The LDS buffer may be reused after this returns only past a __syncthreads().
-template <typename T, int N, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, class Load,
+// store(i, r, b, pos, value); only the passes in between go through LDS.
+// load() is called for all CNT*R elements of a thread before any arithmetic,
+// so their memory requests are in flight together.  For one-pass plans the
+// inputs go straight from load() through the DFT to store().  The LDS buffer
+// may be reused after this returns only past a __syncthreads().
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, class Load,
           class Store>
 __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Load&& load,
                                         Store&& store) {
-  static_assert(plan_ok<N>(), "radix plan does not multiply to N");
-  using FP = FirstPass<N, NB, NT>;
+  static_assert(plan_ok<PL>(), "radix plan does not multiply to N");
+  using FP = FirstPass<PL, NB, NT>;
   cx<T> v[FP::CNT][FP::R];
 #pragma unroll
   for (int i = 0; i < FP::CNT; ++i) {
@@ -318,27 +523,8 @@ __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, in
 #pragma unroll
     for (int r = 0; r < FP::R; ++r) v[i][r] = ok ? load(b, j + r * FP::NBF) : mk<T>(0, 0);
   }
-  fft_first_regs<T, N, NB, NT, ES, BS, S, MAP, PADSH>(buf, v, tid, b_act, store);
-  fft_rest<T, N, NB, NT, ES, BS, S, MAP, PADSH>(buf, tw, tid, b_act, store);
-}
-
-// Per-thread shape of the last pass of fft_reg (for callers that keep its
-// outputs in registers).
-template <int N, int NB, int NT> struct LastPass {
-  static constexpr int R = Plan<N>::r[Plan<N>::np - 1];
-  static constexpr int NBF = N / R;
-  static constexpr int TOT = NB * NBF;
-  static constexpr int CNT = (TOT + NT - 1) / NT;
-};
-
-// Workgroup id remap for gfx950's eight XCDs.  Workgroups are handed out
-// round-robin (id w runs on XCD w mod 8); the returned logical id makes each
-// XCD own one contiguous range, so logically adjacent workgroups share an L2.
-__device__ __forceinline__ int xcd_remap(int w, int total) {
-  constexpr int X = 8;
-  const int per = total / X, rem = total % X;
-  const int xcd = w % X, slot = w / X;
-  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  fft_first_regs<T, PL, NB, NT, ES, BS, S, MAP, PADSH>(buf, v, tid, b_act, store);
+  fft_rest<T, PL, NB, NT, ES, BS, S, MAP, PADSH>(buf, tw, tid, b_act, store);
 }
 
 // Item order of a persistent grid of G workgroups over `total` items: the
@@ -354,6 +540,14 @@ __device__ __forceinline__ int64_t xcd_item(int w, int G, int64_t k, int64_t tot
   const int64_t len = base + (xcd < rem ? 1 : 0);
   const int64_t idx = k * per + slot;
   return idx < len ? start + idx : -1;
+}
+
+// Workgroup id remap for gfx950's eight XCDs (non-persistent grids).
+__device__ __forceinline__ int xcd_remap(int w, int total) {
+  constexpr int X = 8;
+  const int per = total / X, rem = total % X;
+  const int xcd = w % X, slot = w / X;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
 }  // namespace mhd

@@ -157,7 +157,7 @@ bool size_ok(int32_t n, int32_t prec) {
 #undef MHD_LISTED
   if (!listed) return false;
   if (prec == MHD_FP64 && n > 512) return false;
-  return prec == MHD_FP64 || prec == MHD_FP32;
+  return prec == MHD_FP64 || prec == MHD_FP32 || prec == MHD_MIXED;
 }
 
 Geo make_geo(int n) {
@@ -569,9 +569,13 @@ struct Engine {
   }
 };
 
+// Working precision -> element type of the state and of real fields.
+bool is_fp32(int32_t prec) { return prec == MHD_FP32 || prec == MHD_MIXED; }
+
 const void* kern_for(const mhd_ctx* c) {
   Registry& r = registry();
   if (c->p.precision == MHD_FP32) return r.f32[c->p.n].row ? &r.f32[c->p.n] : nullptr;
+  if (c->p.precision == MHD_MIXED) return r.mx[c->p.n].row ? &r.mx[c->p.n] : nullptr;
   return r.f64[c->p.n].row ? &r.f64[c->p.n] : nullptr;
 }
 
@@ -579,7 +583,7 @@ template <typename F>
 int with_engine(mhd_ctx* c, F&& fn) {
   const void* k = kern_for(c);
   if (!k) return MHD_E_SIZE;
-  if (c->p.precision == MHD_FP32) {
+  if (is_fp32(c->p.precision)) {
     Engine<float> e(c, *static_cast<const Kern<float>*>(k));
     return fn(e);
   }
@@ -589,7 +593,7 @@ int with_engine(mhd_ctx* c, F&& fn) {
 
 int validate(const mhd_params* p) {
   if (!p) return MHD_E_ARG;
-  if (p->precision != MHD_FP32 && p->precision != MHD_FP64) return MHD_E_ARG;
+  if (p->precision != MHD_FP32 && p->precision != MHD_FP64 && p->precision != MHD_MIXED) return MHD_E_ARG;
   if (p->reserved != 0) return MHD_E_ARG;
   if (!(p->gamma > 1.0) || !(p->nu >= 0.0) || !(p->eta >= 0.0) || !(p->dt > 0.0) || !(p->cfl > 0.0)) return MHD_E_ARG;
   if (!std::isfinite(p->gamma) || !std::isfinite(p->nu) || !std::isfinite(p->eta) || !std::isfinite(p->dt) ||
@@ -621,7 +625,7 @@ int32_t mhd_spectrum_pitch(int32_t n) {
 
 size_t mhd_workspace_bytes(const mhd_params* p) {
   if (validate(p) != MHD_OK) return 0;
-  const size_t ts = p->precision == MHD_FP32 ? sizeof(float) : sizeof(double);
+  const size_t ts = is_fp32(p->precision) ? sizeof(float) : sizeof(double);
   return make_layout(make_geo(p->n), ts).total;
 }
 
@@ -637,7 +641,7 @@ int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_
   if (!c) return MHD_E_ARG;
   c->p = *p;
   c->g = make_geo(p->n);
-  const size_t ts = p->precision == MHD_FP32 ? sizeof(float) : sizeof(double);
+  const size_t ts = is_fp32(p->precision) ? sizeof(float) : sizeof(double);
   c->L = make_layout(c->g, ts);
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->ws = static_cast<char*>(d_workspace);
@@ -661,26 +665,26 @@ int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_
     }
     const int64_t rows = (int64_t)p->n * p->n / 2;
     for (int m = 0; m < 5; ++m) {
-      const int occ = p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->row_occupancy(m)
-                                               : static_cast<const Kern<double>*>(kv)->row_occupancy(m);
+      const int occ = is_fp32(p->precision) ? static_cast<const Kern<float>*>(kv)->row_occupancy(m)
+                                            : static_cast<const Kern<double>*>(kv)->row_occupancy(m);
       int64_t blocks = (int64_t)occ * c->num_cus;
       if (blocks > rows) blocks = rows;
       c->row_blocks[m] = (int)blocks;
     }
-    const int cocc[3] = {
-        p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(-1, 1)
-                                 : static_cast<const Kern<double>*>(kv)->col_occupancy(-1, 1),
-        p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 1)
-                                 : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 1),
-        p->precision == MHD_FP32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 3)
-                                 : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 3)};
+    const bool f32 = is_fp32(p->precision);
+    const int cocc[3] = {f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(-1, 1)
+                             : static_cast<const Kern<double>*>(kv)->col_occupancy(-1, 1),
+                         f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 1)
+                             : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 1),
+                         f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 3)
+                             : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 3)};
     for (int m = 0; m < 3; ++m) c->col_blocks[m] = cocc[m] * c->num_cus;
   }
   // twiddles exp(-2 pi i j / n) in FP64, rounded once to the working precision
   const int n = p->n;
   const double two_pi = 6.28318530717958647692528676655900577;
   hipError_t e;
-  if (p->precision == MHD_FP32) {
+  if (is_fp32(p->precision)) {
     float* h = new float[2 * (size_t)n];
     for (int j = 0; j < n; ++j) {
       h[2 * j] = (float)std::cos(two_pi * j / n);
@@ -823,10 +827,11 @@ int mhd_fft3d(mhd_ctx* c, int32_t dir, const void* d_in, void* d_out) {
   if (!c || !d_in || !d_out || (dir != 1 && dir != -1)) return MHD_E_ARG;
   return with_engine(c, [&](auto& e) {
     using T = std::remove_pointer_t<decltype(e.state())>;
+    const int32_t rd = is_fp32(c->p.precision) ? MHD_FP32 : MHD_FP64;
     if (dir < 0) {
-      e.forward_real(d_in, c->p.precision, 1, static_cast<T*>(d_out));
+      e.forward_real(d_in, rd, 1, static_cast<T*>(d_out));
     } else {
-      e.inverse_real(static_cast<const T*>(d_in), 1, d_out, c->p.precision);
+      e.inverse_real(static_cast<const T*>(d_in), 1, d_out, rd);
     }
     return check_launch(c, "mhd_fft3d");
   });

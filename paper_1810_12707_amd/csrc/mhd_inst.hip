@@ -10,70 +10,70 @@
 namespace mhd {
 namespace {
 
-template <typename T, int N>
+template <typename T, int N, bool MX>
 void col_inv(int maxt, const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  if (maxt <= 1) hipLaunchKernelGGL((k_col<T, N, 1, 1>), g, dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL((k_col<T, N, 1, kMaxTerms>), g, dim3(kThreads), 0, s, a);
+  if (maxt <= 1) hipLaunchKernelGGL((k_col<T, N, 1, 1, MX>), g, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_col<T, N, 1, kMaxTerms, MX>), g, dim3(kThreads), 0, s, a);
 }
-template <typename T, int N>
+template <typename T, int N, bool MX>
 void col_fwd(const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((k_col<T, N, -1, 1>), g, dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_col<T, N, -1, 1, MX>), g, dim3(kThreads), 0, s, a);
 }
-template <typename T, int N>
+template <typename T, int N, bool MX>
 int col_occupancy(int dir, int maxt) {
   int blocks = 0;
   hipError_t e;
-  if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, -1, 1>, kThreads, 0);
-  else if (maxt <= 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, 1>, kThreads, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, kMaxTerms>, kThreads, 0);
+  if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, -1, 1, MX>, kThreads, 0);
+  else if (maxt <= 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, 1, MX>, kThreads, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, kMaxTerms, MX>, kThreads, 0);
   return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
-template <typename T, int N>
+template <typename T, int N, bool MX>
 void rhs(const RhsArgs<T>& a, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((k_zfwd_rhs<T, N>), g, dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_zfwd_rhs<T, N, MX>), g, dim3(kThreads), 0, s, a);
 }
-template <typename T, int N>
+template <typename T, int N, bool MX>
 void row(int mode, const RowArgs<T>& a, dim3 g, hipStream_t s) {
   switch (mode) {
-    case RM_XA: hipLaunchKernelGGL((k_row<T, N, RM_XA>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XB: hipLaunchKernelGGL((k_row<T, N, RM_XB>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XFWD_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XFWD_REAL>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XINV_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XINV_REAL>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XDIAG: hipLaunchKernelGGL((k_row<T, N, RM_XDIAG>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XA: hipLaunchKernelGGL((k_row<T, N, RM_XA, MX>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XB: hipLaunchKernelGGL((k_row<T, N, RM_XB, MX>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XFWD_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XFWD_REAL, MX>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XINV_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XINV_REAL, MX>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XDIAG: hipLaunchKernelGGL((k_row<T, N, RM_XDIAG, MX>), g, dim3(kThreads), 0, s, a); break;
     default: break;
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, bool MX>
 int row_occupancy(int mode) {
   int blocks = 0;
   hipError_t e = hipSuccess;
   switch (mode) {
-    case RM_XA: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XA>, kThreads, 0); break;
-    case RM_XB: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XB>, kThreads, 0); break;
+    case RM_XA: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XA, MX>, kThreads, 0); break;
+    case RM_XB: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XB, MX>, kThreads, 0); break;
     case RM_XFWD_REAL:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XFWD_REAL>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XFWD_REAL, MX>, kThreads, 0);
       break;
     case RM_XINV_REAL:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XINV_REAL>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XINV_REAL, MX>, kThreads, 0);
       break;
-    case RM_XDIAG: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XDIAG>, kThreads, 0); break;
+    case RM_XDIAG: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XDIAG, MX>, kThreads, 0); break;
     default: break;
   }
   return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 
-template <typename T, int N>
+template <typename T, int N, bool MX>
 Kern<T> make() {
   Kern<T> k;
   k.n = N;
   k.col_width = col_width<T, N>();
-  k.col_inv = col_inv<T, N>;
-  k.col_fwd = col_fwd<T, N>;
-  k.rhs = rhs<T, N>;
-  k.row = row<T, N>;
-  k.row_occupancy = row_occupancy<T, N>;
-  k.col_occupancy = col_occupancy<T, N>;
+  k.col_inv = col_inv<T, N, MX>;
+  k.col_fwd = col_fwd<T, N, MX>;
+  k.rhs = rhs<T, N, MX>;
+  k.row = row<T, N, MX>;
+  k.row_occupancy = row_occupancy<T, N, MX>;
+  k.col_occupancy = col_occupancy<T, N, MX>;
   return k;
 }
 
@@ -82,9 +82,10 @@ Kern<T> make() {
 #define MHD_CAT2(a, b) a##b
 #define MHD_CAT(a, b) MHD_CAT2(a, b)
 void MHD_CAT(register_, MHD_N)(Registry& r) {
-  r.f32[MHD_N] = make<float, MHD_N>();
+  r.f32[MHD_N] = make<float, MHD_N, false>();
+  r.mx[MHD_N] = make<float, MHD_N, true>();
 #if MHD_N <= 512
-  r.f64[MHD_N] = make<double, MHD_N>();
+  r.f64[MHD_N] = make<double, MHD_N, false>();
 #endif
 }
 

@@ -95,11 +95,12 @@ __device__ __forceinline__ TileField tile_field(int nfields) {
 // that were loaded from HBM while the previous item was being transformed
 // (up to MAXT input terms per element; the zero gap of a band input is never
 // loaded); the last pass stores straight to HBM (dropped modes skipped).
-template <typename T, int N, int S, int MAXT>
+template <typename T, int N, int S, int MAXT, bool MX>
 __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
+  using PL = PlanOf<N, MX>;
   constexpr int C = col_width<T, N>();
   constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
-  using FP = FirstPass<N, C, kThreads>;
+  using FP = FirstPass<PL, C, kThreads>;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
@@ -221,22 +222,23 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
       }
       st(out, base_out + l * ls_out + c, val);
     };
-    fft_first_regs<T, N, C, kThreads, C, 1, S, 0, 0>(tile, v, tid, C, store);
+    fft_first_regs<T, PL, C, kThreads, C, 1, S, 0, 0>(tile, v, tid, C, store);
     const int next = (int)xcd_item(blockIdx.x, G, k + 1, total);
     if (next >= 0) issue(decode(next));  // in flight during this item's LDS passes
-    fft_rest<T, N, C, kThreads, C, 1, S, 0, 0>(tile, stw, tid, C, store);
+    fft_rest<T, PL, C, kThreads, C, 1, S, 0, 0>(tile, stw, tid, C, store);
     item = next;
   }
 }
 
 // ------------------------------------------------------------------ k_zfwd_rhs
 // Flat grid over (column tile of (ky, kx), output field f = 0..7), field fastest.
-template <typename T, int N>
+template <typename T, int N, bool MX>
 __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
+  using PL = PlanOf<N, MX>;
   constexpr int C = col_width<T, N>();
   constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
   constexpr int NCOLS = NBB * NHP;  // flattened (ky, kx) over the padded pitch
-  using LP = LastPass<N, C, kThreads>;
+  using LP = LastPass<PL, C, kThreads>;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
@@ -330,7 +332,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
         acc[i][r].y += kz * v.x;
       }
     };
-    fft_reg<T, N, C, kThreads, C, 1, -1>(tile, stw, tid, C, load, store);
+    fft_reg<T, PL, C, kThreads, C, 1, -1>(tile, stw, tid, C, load, store);
   }
   // epilogue over this thread's last-pass positions: resistive term, update
   const T eta = T(a.eta);
@@ -399,15 +401,16 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s,
 // spectral-input modes the global loads of the next row pair's first FFT pass
 // are issued right after the current pair's first pass, so they are in flight
 // during the current pair's LDS passes, pointwise work and stores.
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, bool MX>
 __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
+  using PL = PlanOf<N, MX>;
   constexpr int K = Band<N>::K, NHP = Band<N>::NHP;
   constexpr int NH = Band<N>::NH;
   constexpr int NB = RowShape<MODE>::NB;
   constexpr int PADSH = 3;                    // one LDS padding slot per 8 elements
   constexpr int BS = N + (N >> PADSH) + 1;   // padded row pitch in LDS
   constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
-  using FP = FirstPass<N, NB, kThreads>;
+  using FP = FirstPass<PL, NB, kThreads>;
   auto at = [](int b, int pos) { return lds_at<1, BS, PADSH>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
@@ -505,9 +508,9 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
           v[i][r] = z;
         }
       }
-      fft_first_regs<T, N, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, v, tid, nin, lds_store);
+      fft_first_regs<T, PL, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, v, tid, nin, lds_store);
       if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
-      fft_rest<T, N, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, lds_store);
+      fft_rest<T, PL, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, lds_store);
     }
     __syncthreads();
 
@@ -640,7 +643,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
 
     if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
       __syncthreads();
-      lds_fft<T, N, NB, kThreads, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
+      lds_fft<T, PL, NB, kThreads, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
       // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
       T* out0 = a.out0;
       const int64_t ost = a.out_stride;

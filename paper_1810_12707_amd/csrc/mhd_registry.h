@@ -23,6 +23,7 @@ struct Kern {
 struct Registry {
   Kern<float> f32[1025];
   Kern<double> f64[1025];
+  Kern<float> mx[1025];  // FP32 data, radix-16 stages on MFMA (split BF16 x 3)
 };
 
 Registry& registry();

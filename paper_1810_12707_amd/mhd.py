@@ -19,7 +19,7 @@ LIBPATH = os.path.join(HERE, "_lib", "libmhd.so")
 
 MHD_OK, MHD_E_ARG, MHD_E_SIZE, MHD_E_WORKSPACE, MHD_E_HIP, MHD_E_NONFINITE, MHD_E_CFL, MHD_E_STATE = (
     0, -1, -2, -3, -4, -5, -6, -7)
-MHD_FP64, MHD_FP32 = 0, 1
+MHD_FP64, MHD_FP32, MHD_MIXED = 0, 1, 2
 MHD_FLAG_CHECK_CFL = 1
 
 EXPORTED = (
@@ -233,7 +233,8 @@ class Solver:
 
         self.torch = torch
         self.n = int(n)
-        self.precision = MHD_FP32 if precision in ("fp32", MHD_FP32) else MHD_FP64
+        codes = {"fp64": MHD_FP64, "fp32": MHD_FP32, "mixed": MHD_MIXED}
+        self.precision = codes[precision] if isinstance(precision, str) else int(precision)
         self.params = make_params(n, self.precision, gamma, nu, eta, dt, cfl, flags)
         nbytes = mhd_workspace_bytes(self.params)
         if nbytes == 0:
@@ -244,7 +245,7 @@ class Solver:
         off = (-self.workspace.data_ptr()) % 256
         self._ws = self.workspace[off:off + nbytes]
         self.ctx = mhd_init(self.params, self._ws, self.stream.cuda_stream)
-        self.real_dtype = torch.float32 if self.precision == MHD_FP32 else torch.float64
+        self.real_dtype = torch.float64 if self.precision == MHD_FP64 else torch.float32
 
     @property
     def spectrum_size(self) -> int:
