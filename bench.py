@@ -10,7 +10,9 @@ region.  Inputs are resident in HBM before timing starts.
 Default workload: 256^3 random-phase turbulence (solenoidal u with E(k) ~ k^-2
 in shells 1-8, Mach 0.3; B rms 0.1 in shells 1-4; rho = 1 +- 1%), FP32,
 nu = eta = 2e-3, dt from CFL 0.1.  A secondary 512^3 ABC-dynamo line
-(nu = eta = 1e-3) is measured the same way and reported under "secondary".
+(nu = eta = 1e-3) is measured the same way and reported under "secondary", and
+the batched ensemble (64 runs of 32^3..128^3 in one graph per step) against
+the same runs advanced one after another under "ensemble".
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
 build runs on one GPU.
@@ -28,7 +30,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
-PASS_NAMES = ("zinv_a", "yinv_a", "xa", "yfwd_a", "zfwd_a", "zinv_b", "yinv_b", "xb", "yfwd_b", "zrhs", "reduce")
+PASS_NAMES = ("zinv_a", "yinv_a", "xa", "yfwd_a", "zfwd_a", "zinv_b", "yinv_b", "xb", "yfwd_b", "zrhs", "rho",
+              "reduce")
 PASS_KERNELS = {
     "zinv_a": "k_col<float,N,1> (inverse z, 4 fields)",
     "yinv_a": "k_col<float,N,1> (inverse y, 4 fields)",
@@ -40,6 +43,7 @@ PASS_KERNELS = {
     "xb": "k_row<float,N,RM_XB>",
     "yfwd_b": "k_col<float,N,-1> (forward y, 12 fields)",
     "zrhs": "k_zfwd_rhs<float,N>",
+    "rho": "k_rho_rhs<float>",
     "reduce": "k_reduce",
 }
 
@@ -212,6 +216,82 @@ def load_traffic(n: int):
     return rec.get("bytes_per_launch")
 
 
+def ensemble_run(count: int, steps: int, warmup: int):
+    """The batched ensemble (64 runs: 16 each of 32^3, 64^3, 96^3, 128^3,
+    seeds 0-63, nu = eta log-uniform in [1e-3, 1e-2], FP32) advanced by
+    mhd_ens_step, against the same runs advanced one after another by
+    single contexts (same steps, same stream, timed the same way)."""
+    import torch
+
+    from paper_1810_12707_amd import inputs as I
+    from paper_1810_12707_amd.mhd import Ensemble, Solver
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    cases = I.config_ensemble(count)
+    log(f"[bench] ensemble inputs: {count} runs in {time.perf_counter() - t0:.1f} s")
+    points = sum(c.n ** 3 for c in cases)
+    E = Ensemble([{"n": c.n, "precision": "fp32", "gamma": c.gamma, "nu": c.nu, "eta": c.eta, "dt": c.dt}
+                  for c in cases], device=dev)
+    for i, c in enumerate(cases):
+        E.set_state(i, torch.from_numpy(c.U).to(dev))
+    t0 = time.perf_counter()
+    E.step(warmup)  # tuning, the Euler start, graph capture
+    torch.cuda.synchronize()
+    log(f"[bench] ensemble warm-up (tuning + capture) {time.perf_counter() - t0:.2f} s; groups {E.groups()}")
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    E.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ens_ms = e0.elapsed_time(e1)
+    rc, st, _ = E.diagnostics()
+    check = E.get_state(count - 1)
+    groups = E.groups()
+    step_bytes = E.step_bytes
+    E.close()
+    del E
+    torch.cuda.empty_cache()
+    log(f"[bench] ensemble {ens_ms / steps:.3f} ms/step")
+
+    solos = []
+    for c in cases:
+        S = Solver(c.n, precision="fp32", gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt, device=dev)
+        S.set_state(torch.from_numpy(c.U).to(dev))
+        S.step(warmup)
+        solos.append(S)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for S in solos:
+        S.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1)
+    same = bool(torch.equal(check, solos[-1].get_state()))
+    for S in solos:
+        S.close()
+    del solos
+    torch.cuda.empty_cache()
+    log(f"[bench] sequential {seq_ms / steps:.3f} ms/step; last member bitwise equal: {same}")
+    ens_rate = points * steps / (ens_ms * 1e-3)
+    seq_rate = points * steps / (seq_ms * 1e-3)
+    return {
+        "workload": f"{count} independent FP32 runs: 16 each of 32^3, 64^3, 96^3, 128^3 "
+                    f"({points / 1e6:.1f} M points), random-phase turbulence seeds 0-{count - 1}, "
+                    "nu = eta log-uniform in [1e-3, 1e-2], dt from CFL 0.1 per run, AB2",
+        "value": round(ens_rate, 1), "unit": "grid-point-steps/s (sum over runs)",
+        "ms_per_step": round(ens_ms / steps, 4), "steps": steps, "warmup": warmup,
+        "sequential": {"value": round(seq_rate, 1), "ms_per_step": round(seq_ms / steps, 4),
+                       "what": "the same runs, each advanced by its own context, one after another"},
+        "speedup_vs_sequential": round(ens_rate / seq_rate, 3),
+        "step_hbm": {"alg_bytes_per_step": step_bytes,
+                     "GBps": round(step_bytes / (ens_ms * 1e-3 / steps) / 1e9, 1),
+                     "frac": round(step_bytes / (ens_ms * 1e-3 / steps) / 1e9 / HBM_PEAK_GBS, 4)},
+        "groups": groups, "status": rc, "last_member_bitwise_equal_to_solo": same,
+    }
+
+
 def cpu_baseline(n_sample: int = 128):
     """The FP64 CPU oracle (as it stands) on one AB2 step of the same
     random-turbulence recipe at n_sample^3, scaled to grid-point-steps/s."""
@@ -239,6 +319,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-error", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=20, help="steps of the batched-ensemble line (0 = none)")
+    ap.add_argument("--ensemble-count", type=int, default=64)
     a = ap.parse_args(argv)
 
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -286,6 +368,11 @@ def main(argv=None):
         log(f"[bench] secondary {secondary['ms_per_step']} ms/step")
         del c2
 
+    ensemble = None
+    if a.ensemble_steps > 0:
+        log(f"[bench] batched ensemble of {a.ensemble_count} runs")
+        ensemble = ensemble_run(a.ensemble_count, a.ensemble_steps, 3)
+
     cpu = None
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
@@ -317,6 +404,7 @@ def main(argv=None):
         "status": r["rc"],
         "wall_s": round(r["wall_s"], 4),
         "secondary": secondary,
+        "ensemble": ensemble,
     }
     print(json.dumps(out), flush=True)
     return 0

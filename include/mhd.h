@@ -164,11 +164,13 @@ int64_t mhd_spectrum_size(int32_t n);
 int32_t mhd_spectrum_pitch(int32_t n);
 
 /* Launch classes of one step, for mhd_profile_read.  Suffix _A: phase A
- * (u^ = D F[m/rho]); _B: phase B (fluxes and update). */
+ * (u^ = D F[m/rho]); _B: phase B (fluxes and update); ZRHS: forward z with
+ * the momentum, induction and energy right-hand sides and their update; RHO:
+ * the density right-hand side -i k.m^ and its update. */
 enum {
     MHD_PASS_ZINV_A = 0, MHD_PASS_YINV_A, MHD_PASS_XA, MHD_PASS_YFWD_A, MHD_PASS_ZFWD_A,
     MHD_PASS_ZINV_B, MHD_PASS_YINV_B, MHD_PASS_XB, MHD_PASS_YFWD_B, MHD_PASS_ZRHS,
-    MHD_PASS_REDUCE, MHD_PASS_COUNT
+    MHD_PASS_RHO, MHD_PASS_REDUCE, MHD_PASS_COUNT
 };
 
 /* Benchmark hook (not physics): enable = 1 clears the counters and brackets
@@ -197,6 +199,74 @@ const char* mhd_status_string(int status);
 
 /* Text of the last HIP error seen by ctx ("" if none). */
 const char* mhd_last_error(const mhd_ctx* ctx);
+
+/* ---------------------------------------------------------------- ensembles
+ *
+ * An ensemble advances `count` independent runs of the same equations
+ * (Eqs. MHD1-MHD4, AB2 stepping as in mhd_step), each with its own grid size,
+ * precision, nu, eta, gamma and dt.  Members with equal (n, precision) form a
+ * group of at most 64 whose passes run as one persistent launch per pass over
+ * all of the group's members; groups run as parallel branches of one HIP
+ * graph, replayed once per step.  Each member's arithmetic is exactly that of
+ * a single context with the same parameters, so a member's state matches a
+ * solo run bit for bit, and a non-finite value in one member never reaches
+ * another.  The paper runs one simulation at a time; the ensemble is an
+ * extension of the same per-step operator. */
+typedef struct mhd_ens mhd_ens;
+
+/* Bytes of device workspace for the members p[0..count-1] (count >= 1), or 0
+ * if any member's parameters are invalid. */
+size_t mhd_ens_workspace_bytes(const mhd_params* p, int32_t count);
+
+/* Creates an ensemble.  d_workspace: caller-owned device memory of at least
+ * mhd_ens_workspace_bytes(p, count) bytes, 256-byte aligned; every call
+ * enqueues on hip_stream (NULL = default stream).  The ensemble creates one
+ * extra stream per group (default priority) for the graph's branches.
+ * tune_cache_path: text file of tuned launch geometries (read at init,
+ * appended to after tuning); NULL keeps tuning results in memory only; an
+ * empty string "" turns tuning off (every pass uses its resident-occupancy
+ * grid).  Tuning runs at the first mhd_ens_step with all states set and
+ * evaluates right-hand sides only, so it leaves every state unchanged. */
+int mhd_ens_init(const mhd_params* p, int32_t count, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                 const char* tune_cache_path, mhd_ens** out);
+
+/* Sets member `member`'s state from real fields ([8][n][n][n], element type
+ * dtype) exactly as mhd_set_state does for a context. */
+int mhd_ens_set_state(mhd_ens* ens, int32_t member, const void* d_fields, int32_t dtype);
+
+/* Writes member `member`'s state as real fields, as mhd_get_state. */
+int mhd_ens_get_state(mhd_ens* ens, int32_t member, void* d_fields, int32_t dtype);
+
+/* Advances every member by nsteps >= 0 steps (MHD_E_STATE unless every
+ * member has a state).  A step in which some member takes its first (Euler)
+ * step runs eagerly; every other step replays the captured graph. */
+int mhd_ens_step(mhd_ens* ens, int32_t nsteps);
+
+/* Diagnostics of every member into h_out[count] (host) and each member's
+ * status (as mhd_diagnostics would return it) into h_status[count] (host,
+ * may be NULL); synchronises the stream.  Returns MHD_OK when every member
+ * is finite and within its CFL limit, else the first member's failing
+ * status. */
+int mhd_ens_diagnostics(mhd_ens* ens, mhd_diag* h_out, int32_t* h_status);
+
+/* Number of member groups (equal n and precision, at most 64 members). */
+int32_t mhd_ens_num_groups(const mhd_ens* ens);
+
+/* Group g's grid size, precision, member count and tuned persistent-grid
+ * scales (column passes, row passes; 1 = resident-occupancy grid).  Any
+ * output pointer may be NULL. */
+int mhd_ens_group_info(const mhd_ens* ens, int32_t g, int32_t* n, int32_t* precision, int32_t* members,
+                       double* col_scale, double* row_scale);
+
+/* Algorithmic HBM bytes of one mhd_ens_step over all members. */
+double mhd_ens_step_bytes(const mhd_ens* ens);
+
+/* Releases the ensemble's host state, streams, events and graph (not the
+ * caller's workspace). */
+int mhd_ens_destroy(mhd_ens* ens);
+
+/* Text of the last HIP error seen by the ensemble ("" if none). */
+const char* mhd_ens_last_error(const mhd_ens* ens);
 
 #ifdef __cplusplus
 }

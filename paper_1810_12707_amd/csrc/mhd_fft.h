@@ -374,6 +374,63 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
   __syncthreads();
 }
 
+// Last radix-16 pass on the MFMA units.  In the last Stockham pass every
+// butterfly writes its outputs onto its own input positions (d = j), so the
+// groups need no common barrier: each group of 16 butterflies is read,
+// multiplied and handed to store(s, t, b, pos, value) (s = group slot of this
+// wave, t = 0..3 the lane's four outputs) before the next group is read.
+// store() may write the LDS positions in place.
+template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH, class Store>
+__device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const float2* tw, int tid, int b_act,
+                                                   Store&& store) {
+  constexpr int N = PL::N;
+  constexpr int R = 16;
+  constexpr int NS = plan_ns<PL>(P);
+  static_assert(NS * R == N, "the in-place MFMA pass must be the last pass");
+  constexpr int NBF = N / R;
+  constexpr int TOT = NB * NBF;
+  constexpr int NGRP = (TOT + 15) / 16;
+  constexpr int NW = NT / 64;
+  constexpr int GPW = (NGRP + NW - 1) / NW;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int n = lane & 15, g = lane >> 4;
+  bf16x8 a0h, a0l, a1h, a1l;
+  dft16_operands<S>(lane, a0h, a0l, a1h, a1l);
+#pragma unroll
+  for (int s = 0; s < GPW; ++s) {
+    const int grp = wv + s * NW;
+    const int w = grp * 16 + n;
+    int b, j;
+    lane_map<NB, NBF, MAP>(w, b, j);
+    const bool ok = grp < NGRP && w < TOT && b < b_act;
+    bf16x8 xh, xl;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int r = 8 * (g & 1) + t;
+      float2 x = ok ? buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)] : make_float2(0.f, 0.f);
+      if (r > 0) {
+        const float2 tv = tw[j * r];  // k = j in the last pass
+        x = (S < 0) ? cmul(x, tv) : cmulc(x, tv);
+      }
+      const float val = g < 2 ? x.x : x.y;
+      const __bf16 h = (__bf16)val;
+      xh[t] = h;
+      xl[t] = (__bf16)(val - (float)h);
+    }
+    floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, xh, c0, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, xl, c0, 0, 0, 0);
+    c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, xh, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, xh, c1, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, xl, c1, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1l, xh, c1, 0, 0, 0);
+    if (ok) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) store(s, t, b, j + (4 * g + t) * NS, make_float2(c0[t], c1[t]));
+    }
+  }
+}
+
 template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0, int PADSH = 0>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   if constexpr (PL::MX && PL::r[P] == 16) {
@@ -385,13 +442,21 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
   }
 }
 
-// All passes LDS to LDS.
+// All passes LDS to LDS (an MFMA last pass runs in place, group by group).
 template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, int P = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   static_assert(plan_ok<PL>(), "radix plan does not multiply to N");
   if constexpr (P < PL::np) {
-    fft_pass<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
-    lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
+    if constexpr (PL::MX && PL::r[P] == 16 && P == PL::np - 1 && P > 0) {
+      float2* fb = reinterpret_cast<float2*>(buf);
+      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, P, MAP, PADSH>(
+          fb, reinterpret_cast<const float2*>(tw), tid, b_act,
+          [&](int, int, int b, int pos, float2 v) { fb[lds_at<ES, BS, PADSH>(b, pos)] = v; });
+      __syncthreads();
+    } else {
+      fft_pass<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
+      lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
+    }
   }
 }
 
@@ -413,13 +478,42 @@ template <class PL, int NB, int NT> struct FirstPass {
   static constexpr int CNT = (TOT + NT - 1) / NT;
 };
 
-// Per-thread shape of the last pass (outputs handed to store(i, r, ...)).
+// Per-thread shape of the last pass: outputs are handed to store(i, r, ...)
+// for CNT slots i of R outputs r.  VALU last pass: slot i is the thread's i-th
+// butterfly and r its R outputs.  MFMA radix-16 last pass: slot i is the
+// wave's i-th group of 16 butterflies and r the lane's four outputs.
 template <class PL, int NB, int NT> struct LastPass {
-  static constexpr int R = PL::r[PL::np - 1];
-  static constexpr int NBF = PL::N / R;
+  static constexpr int RL = PL::r[PL::np - 1];
+  static constexpr bool MFMA = PL::MX && RL == 16 && PL::np > 1;
+  static constexpr int NBF = PL::N / RL;
   static constexpr int TOT = NB * NBF;
-  static constexpr int CNT = (TOT + NT - 1) / NT;
+  static constexpr int NGRP = (TOT + 15) / 16;
+  static constexpr int NW = NT / 64;
+  static constexpr int CNT = MFMA ? (NGRP + NW - 1) / NW : (TOT + NT - 1) / NT;
+  static constexpr int R = MFMA ? 4 : RL;
 };
+
+// (sequence b, position pos) of output slot (i, r) of this thread in the last
+// pass; false if the slot is idle.
+template <class PL, int NB, int NT, int MAP>
+__device__ __forceinline__ bool last_slot(int tid, int i, int r, int& b, int& pos) {
+  using LP = LastPass<PL, NB, NT>;
+  constexpr int NS = PL::N / LP::RL;
+  int j;
+  if constexpr (LP::MFMA) {
+    const int lane = tid & 63, wv = tid >> 6, n = lane & 15, g = lane >> 4;
+    const int grp = wv + i * LP::NW;
+    const int w = grp * 16 + n;
+    lane_map<NB, LP::NBF, MAP>(w, b, j);
+    pos = j + (4 * g + r) * NS;
+    return grp < LP::NGRP && w < LP::TOT;
+  } else {
+    const int w = tid + i * NT;
+    lane_map<NB, LP::NBF, MAP>(w, b, j);
+    pos = j + r * NS;
+    return LP::TOT % NT == 0 || w < LP::TOT;
+  }
+}
 
 // First pass from values already in registers (v[i][r] = element j + r*NBF of
 // sequence b for this thread's i-th butterfly): R-point DFTs, then either the
@@ -465,17 +559,14 @@ __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, i
     constexpr int TOT = NB * NBF;
     constexpr int CNT = (TOT + NT - 1) / NT;
     if constexpr (PL::MX && R == 16) {
-      fft_pass<T, PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH>(buf, tw, tid, b_act);
-#pragma unroll
-      for (int i = 0; i < CNT; ++i) {
-        const int w = tid + i * NT;
-        int b, j;
-        lane_map<NB, NBF, MAP>(w, b, j);
-        if ((TOT % NT == 0 || w < TOT) && b < b_act) {
-#pragma unroll
-          for (int r = 0; r < R; ++r) store(i, r, b, j + r * NS, buf[lds_at<ES, BS, PADSH>(b, j + r * NS)]);
-        }
-      }
+      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH>(
+          reinterpret_cast<const float2*>(buf), reinterpret_cast<const float2*>(tw), tid, b_act,
+          [&](int i, int r, int b, int pos, float2 v) {
+            cx<T> vv;
+            vv.x = v.x;
+            vv.y = v.y;
+            store(i, r, b, pos, vv);
+          });
     } else {
 #pragma unroll
       for (int i = 0; i < CNT; ++i) {

@@ -87,6 +87,51 @@ k_reduce(const double* __restrict__ part, int64_t nrec, int nq, unsigned max_mas
 
 // Spectral sums over the compact B^ (half spectrum: kx > 0 modes count twice):
 // sum Re(J^ . conj B^)/|k|^2, sum |i k.B^|^2, sum |J^|^2 with J^ = i k x B^.
+// Eq. MHD1 in spectral form, R_rho = -i k . m^, with the density's AB2
+// update U_rho += dt (a_cur R + a_prev R_prev), R_prev <- R, or the store of
+// R into rout.  One thread per compact entry (padding skipped) of member
+// blockIdx.y.  Launched before the forward-z pass that forms the other seven
+// right-hand sides, since that pass overwrites m^ with its next time level.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rho_rhs(const RhsArgs<T> a) {
+  using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+  const Geo& g = a.g;
+  const int mem = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t plane = (int64_t)g.nb * g.nhp;
+  const int lz = (int)(idx / plane);
+  const int rem = (int)(idx - (int64_t)lz * plane);
+  const int ly = rem / g.nhp, kx = rem - ly * g.nhp;
+  if (idx >= g.sc || kx >= g.nh) return;
+  const int kz = lz <= g.K ? lz : lz - g.nb;
+  const int ky = ly <= g.K ? ly : ly - g.nb;
+  const int64_t ms = a.bt.mstride;
+  V2* const state = reinterpret_cast<V2*>(member_ptr(a.state, mem, ms));
+  const V2 mx = state[g.sc + idx], my = state[2 * g.sc + idx], mz = state[3 * g.sc + idx];
+  const T dx = T(kx) * mx.x + T(ky) * my.x + T(kz) * mz.x;
+  const T dy = T(kx) * mx.y + T(ky) * my.y + T(kz) * mz.y;
+  V2 R;
+  R.x = dy;  // -i (dx + i dy)
+  R.y = -dx;
+  if (a.rout) {
+    reinterpret_cast<V2*>(member_ptr(a.rout, mem, ms))[idx] = R;
+    return;
+  }
+  V2* const rprev = reinterpret_cast<V2*>(member_ptr(a.rprev, mem, ms));
+  const T dt = T(a.dt[mem]), ac = T(a.a_cur[mem]), ap = T(a.a_prev[mem]);
+  T ir = R.x * ac, ii = R.y * ac;
+  if (a.a_prev[mem] != 0.0) {
+    const V2 p = rprev[idx];
+    ir += p.x * ap;
+    ii += p.y * ap;
+  }
+  V2 u = state[idx];
+  u.x += dt * ir;
+  u.y += dt * ii;
+  state[idx] = u;
+  rprev[idx] = R;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz, Geo g,
@@ -216,7 +261,7 @@ struct mhd_ctx {
   int64_t step;
   double t;
   int num_cus = 0;
-  int row_blocks[5] = {0, 0, 0, 0, 0};  // persistent grid of each row-pass mode
+  int row_blocks[5] = {0, 0, 0, 0, 0};  // resident workgroups of each row-pass mode
   int col_blocks[3] = {0, 0, 0};        // column passes: forward, inverse (1 term), inverse (3 terms)
   std::string last_err;
   // benchmark timing (mhd_profile)
@@ -261,13 +306,38 @@ OutSpec spec(std::initializer_list<Term> ts) {
 
 OutSpec copy_spec(int src, double coef) { return spec({term(src, -1, coef)}); }
 
+// The members one engine runs per launch: member 0 is the engine's context,
+// member m sits at byte offset m * stride; per-member physical parameters,
+// AB2 coefficients of the current step, and the launch-geometry scales picked
+// by the ensemble autotuner.
+struct MemberSet {
+  int n = 1;
+  int64_t stride = 0;
+  double gamma[kMaxMem], nu[kMaxMem], eta[kMaxMem], dt[kMaxMem];
+  double a_cur[kMaxMem], a_prev[kMaxMem];
+  double col_scale = 1.0, row_scale = 1.0;
+};
+
+MemberSet single_member(const mhd_ctx* c) {
+  MemberSet m;
+  m.gamma[0] = c->p.gamma;
+  m.nu[0] = c->p.nu;
+  m.eta[0] = c->p.eta;
+  m.dt[0] = c->p.dt;
+  m.a_cur[0] = 1.0;
+  m.a_prev[0] = 0.0;
+  return m;
+}
+
 template <typename T>
 struct Engine {
   mhd_ctx* c;
   const Kern<T>& k;
   const Geo& g;
+  MemberSet ms;
 
-  Engine(mhd_ctx* ctx, const Kern<T>& kern) : c(ctx), k(kern), g(ctx->g) {}
+  Engine(mhd_ctx* ctx, const Kern<T>& kern) : c(ctx), k(kern), g(ctx->g), ms(single_member(ctx)) {}
+  Engine(mhd_ctx* ctx, const Kern<T>& kern, const MemberSet& m) : c(ctx), k(kern), g(ctx->g), ms(m) {}
 
   T* at(size_t off) const { return reinterpret_cast<T*>(c->ws + off); }
   T* state() const { return at(c->L.state); }
@@ -301,7 +371,8 @@ struct Engine {
       case MHD_PASS_YINV_B: return cbytes(0, 12, 12);
       case MHD_PASS_XB: return cbytes(0, 0, 28);
       case MHD_PASS_YFWD_B: return cbytes(0, 12, 12);
-      case MHD_PASS_ZRHS: return cbytes(32, 12, 0);
+      case MHD_PASS_ZRHS: return cbytes(28, 12, 0);
+      case MHD_PASS_RHO: return cbytes(7, 0, 0);
       case MHD_PASS_REDUCE: return 0.0;
       default: return 0.0;
     }
@@ -312,9 +383,9 @@ struct Engine {
   void timed(int cls, F&& launch) {
     if (c->prof_on && c->nrec < (int)c->rec_cls.size()) {
       const int r = c->nrec++;
-      hipEventRecord(c->ev[2 * r], c->stream);
+      (void)hipEventRecord(c->ev[2 * r], c->stream);
       launch();
-      hipEventRecord(c->ev[2 * r + 1], c->stream);
+      (void)hipEventRecord(c->ev[2 * r + 1], c->stream);
       c->rec_cls[r] = cls;
       c->rec_bytes[r] = class_bytes(cls);
     } else {
@@ -326,6 +397,14 @@ struct Engine {
   int ztiles() const { return (int)(((int64_t)g.nb * g.nhp + k.col_width - 1) / k.col_width); }
   int ytiles() const { return (g.nh + k.col_width - 1) / k.col_width; }
 
+  Batch batch() const {
+    Batch b;
+    b.nmem = ms.n;
+    b.pad = 0;
+    b.mstride = ms.stride;
+    return b;
+  }
+
   ColArgs<T> col_args(int kind, int nout) const {
     ColArgs<T> a;
     std::memset(&a, 0, sizeof(a));
@@ -333,6 +412,7 @@ struct Engine {
     a.nout = nout;
     a.tw = tw();
     a.g = g;
+    a.bt = batch();
     return a;
   }
 
@@ -349,8 +429,9 @@ struct Engine {
     }
     const bool z = (kind == PK_ZINV || kind == PK_ZFWD);
     const bool inv = (kind == PK_ZINV || kind == PK_YINV);
-    const int64_t items = (int64_t)(z ? ztiles() : g.n * ytiles()) * nout;
-    int64_t blocks = (int64_t)c->col_blocks[inv ? (maxt > 1 ? 2 : 1) : 0];
+    const int64_t items = (int64_t)(z ? ztiles() : g.n * ytiles()) * nout * ms.n;
+    int64_t blocks = (int64_t)(c->col_blocks[inv ? (maxt > 1 ? 2 : 1) : 0] * ms.col_scale);
+    if (blocks < 1) blocks = 1;
     if (blocks > items) blocks = items;
     dim3 grid((unsigned)blocks);
     if (inv) k.col_inv(maxt, a, grid, c->stream);
@@ -367,16 +448,26 @@ struct Engine {
   RowArgs<T> row_args() const {
     RowArgs<T> a;
     std::memset(&a, 0, sizeof(a));
-    a.gamma = c->p.gamma;
-    a.nu = c->p.nu;
-    a.eta = c->p.eta;
+    for (int m = 0; m < ms.n; ++m) {
+      a.gamma[m] = ms.gamma[m];
+      a.nu[m] = ms.nu[m];
+      a.eta[m] = ms.eta[m];
+    }
     a.tw = tw();
     a.g = g;
+    a.bt = batch();
     return a;
   }
 
-  // Persistent row passes: as many workgroups as can be resident at once.
-  dim3 row_grid(int mode) const { return dim3((unsigned)c->row_blocks[mode]); }
+  // Persistent row passes: as many workgroups as can be resident at once
+  // (scaled by the tuned factor), capped by the number of row pairs.
+  dim3 row_grid(int mode) const {
+    int64_t blocks = (int64_t)(c->row_blocks[mode] * ms.row_scale);
+    const int64_t items = (int64_t)g.n * g.n / 2 * ms.n;
+    if (blocks < 1) blocks = 1;
+    if (blocks > items) blocks = items;
+    return dim3((unsigned)blocks);
+  }
 
   // Row passes address consecutive I_y slots from a first slot and a stride.
   void set_in(RowArgs<T>& r, int first_slot) const {
@@ -457,8 +548,9 @@ struct Engine {
   }
 
   // Phase B: fluxes and the spectral RHS of state U.  rout == nullptr: AB2
-  // update of U and the history with coefficients (a_cur, a_prev).
-  void phase_b(T* U, T* rout, double a_cur, double a_prev) {
+  // update of U and the history with the members' coefficients ms.a_cur,
+  // ms.a_prev.
+  void phase_b(T* U, T* rout) {
     const double s = inv_n3();
     // inputs: 0-2 B^, 3 E^, 4-6 u^
     const T* zi[7] = {spec_field(U, 4), spec_field(U, 5), spec_field(U, 6), spec_field(U, 7),
@@ -517,12 +609,19 @@ struct Engine {
     q.rprev = rprev();
     q.rout = rout;
     q.tw = tw();
-    q.dt = c->p.dt;
-    q.a_cur = a_cur;
-    q.a_prev = a_prev;
-    q.eta = c->p.eta;
+    for (int m = 0; m < ms.n; ++m) {
+      q.dt[m] = ms.dt[m];
+      q.a_cur[m] = ms.a_cur[m];
+      q.a_prev[m] = ms.a_prev[m];
+      q.eta[m] = ms.eta[m];
+    }
     q.g = g;
-    timed(MHD_PASS_ZRHS, [&] { k.rhs(q, dim3((unsigned)(ztiles() * 8)), c->stream); });
+    q.bt = batch();
+    const unsigned sblocks = (unsigned)((g.sc + kThreads - 1) / kThreads);
+    timed(MHD_PASS_RHO, [&] {
+      hipLaunchKernelGGL((k_rho_rhs<T>), dim3(sblocks, (unsigned)ms.n), dim3(kThreads), 0, c->stream, q);
+    });
+    timed(MHD_PASS_ZRHS, [&] { k.rhs(q, dim3((unsigned)(ztiles() * 7 * ms.n)), c->stream); });
   }
 
   double step_bytes() const {
@@ -557,10 +656,11 @@ struct Engine {
     RowArgs<T> r = row_args();
     set_in(r, 0);
     r.partials = part();
-    k.row(RM_XDIAG, r, row_grid(RM_XDIAG), c->stream);
+    const dim3 grid = row_grid(RM_XDIAG);  // one partial record per workgroup (<= n^2/2)
+    k.row(RM_XDIAG, r, grid, c->stream);
     const unsigned maxmask = (1u << DQ_DIVB_MAX) | (1u << DQ_CFL_MAX);
-    hipLaunchKernelGGL(k_reduce, dim3(kDiagQ), dim3(kThreads), 0, c->stream, part(), (int64_t)c->row_blocks[RM_XDIAG],
-                       kDiagQ, maxmask, 0, res());
+    hipLaunchKernelGGL(k_reduce, dim3(kDiagQ), dim3(kThreads), 0, c->stream, part(), (int64_t)grid.x, kDiagQ,
+                       maxmask, 0, res());
     const int sblocks = (int)((g.sc + kThreads - 1) / kThreads);
     hipLaunchKernelGGL((k_spec_diag<T>), dim3(sblocks), dim3(kThreads), 0, c->stream, spec_field(U, 4),
                        spec_field(U, 5), spec_field(U, 6), g, part());
@@ -607,29 +707,7 @@ bool dtype_ok(int32_t d) { return d == MHD_FP32 || d == MHD_FP64; }
 
 }  // namespace
 
-// ------------------------------------------------------------------ C-ABI
-
-extern "C" {
-
-int mhd_supported_size(int32_t n, int32_t precision) { return size_ok(n, precision) ? 1 : 0; }
-
-int64_t mhd_spectrum_size(int32_t n) {
-  if (n < 1) return 0;
-  return make_geo(n).sc;
-}
-
-int32_t mhd_spectrum_pitch(int32_t n) {
-  if (n < 1) return 0;
-  return make_geo(n).nhp;
-}
-
-size_t mhd_workspace_bytes(const mhd_params* p) {
-  if (validate(p) != MHD_OK) return 0;
-  const size_t ts = is_fp32(p->precision) ? sizeof(float) : sizeof(double);
-  return make_layout(make_geo(p->n), ts).total;
-}
-
-int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream, mhd_ctx** out) {
+static int ctx_create(const mhd_params* p, void* d_workspace, size_t ws_bytes, hipStream_t stream, mhd_ctx** out) {
   if (!out) return MHD_E_ARG;
   *out = nullptr;
   int v = validate(p);
@@ -643,7 +721,7 @@ int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_
   c->g = make_geo(p->n);
   const size_t ts = is_fp32(p->precision) ? sizeof(float) : sizeof(double);
   c->L = make_layout(c->g, ts);
-  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->stream = stream;
   c->ws = static_cast<char*>(d_workspace);
   c->ws_bytes = ws_bytes;
   c->has_state = false;
@@ -663,13 +741,10 @@ int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_
       delete c;
       return MHD_E_HIP;
     }
-    const int64_t rows = (int64_t)p->n * p->n / 2;
     for (int m = 0; m < 5; ++m) {
       const int occ = is_fp32(p->precision) ? static_cast<const Kern<float>*>(kv)->row_occupancy(m)
                                             : static_cast<const Kern<double>*>(kv)->row_occupancy(m);
-      int64_t blocks = (int64_t)occ * c->num_cus;
-      if (blocks > rows) blocks = rows;
-      c->row_blocks[m] = (int)blocks;
+      c->row_blocks[m] = occ * c->num_cus;
     }
     const bool f32 = is_fp32(p->precision);
     const int cocc[3] = {f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(-1, 1)
@@ -711,62 +786,7 @@ int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_
   return MHD_OK;
 }
 
-int mhd_set_state(mhd_ctx* c, const void* d_fields, int32_t dtype) {
-  if (!c || !d_fields || !dtype_ok(dtype)) return MHD_E_ARG;
-  int rc = with_engine(c, [&](auto& e) {
-    e.forward_real(d_fields, dtype, 8, e.state());
-    e.reset_status();
-    return check_launch(c, "mhd_set_state");
-  });
-  if (rc == MHD_OK) {
-    c->has_state = true;
-    c->first_step = true;
-    c->step = 0;
-    c->t = 0.0;
-  }
-  return rc;
-}
-
-int mhd_get_state(mhd_ctx* c, void* d_fields, int32_t dtype) {
-  if (!c || !d_fields || !dtype_ok(dtype)) return MHD_E_ARG;
-  if (!c->has_state) return MHD_E_STATE;
-  return with_engine(c, [&](auto& e) {
-    e.inverse_real(e.state(), 8, d_fields, dtype);
-    return check_launch(c, "mhd_get_state");
-  });
-}
-
-int mhd_rhs(mhd_ctx* c, const void* d_in, void* d_out, int32_t dtype) {
-  if (!c || !d_in || !d_out || !dtype_ok(dtype)) return MHD_E_ARG;
-  return with_engine(c, [&](auto& e) {
-    e.forward_real(d_in, dtype, 8, e.tstate());
-    e.phase_a(e.tstate());
-    e.phase_b(e.tstate(), e.trhs(), 1.0, 0.0);
-    e.inverse_real(e.trhs(), 8, d_out, dtype);
-    return check_launch(c, "mhd_rhs");
-  });
-}
-
-int mhd_step(mhd_ctx* c, int32_t nsteps) {
-  if (!c || nsteps < 0) return MHD_E_ARG;
-  if (!c->has_state) return MHD_E_STATE;
-  int rc = with_engine(c, [&](auto& e) {
-    for (int s = 0; s < nsteps; ++s) {
-      const bool first = c->first_step && s == 0;
-      e.phase_a(e.state());
-      e.phase_b(e.state(), nullptr, first ? 1.0 : 1.5, first ? 0.0 : -0.5);
-    }
-    return check_launch(c, "mhd_step");
-  });
-  if (rc == MHD_OK && nsteps > 0) {
-    c->first_step = false;
-    c->step += nsteps;
-    c->t += nsteps * c->p.dt;
-  }
-  return rc;
-}
-
-int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) {
+static int ctx_diag(mhd_ctx* c, mhd_diag* h) {
   if (!c || !h) return MHD_E_ARG;
   if (!c->has_state) return MHD_E_STATE;
   int rc = with_engine(c, [&](auto& e) {
@@ -822,6 +842,325 @@ int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) {
   }
   return MHD_OK;
 }
+
+// ------------------------------------------------------------------ ensembles
+
+// Members with equal (n, precision), at most kMaxMem of them, share one
+// launch per pass: their workspaces sit at a uniform stride from the group's
+// base, and `lead` is a context over the first slot whose stream is the
+// group's branch stream.
+struct EnsGroup {
+  int32_t n = 0, precision = 0;
+  std::vector<int> members;  // ensemble member index of each slot
+  size_t stride = 0;         // bytes between consecutive slots' workspaces
+  char* base = nullptr;
+  mhd_ctx* lead = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  double col_scale = 1.0, row_scale = 1.0;  // persistent-grid scales (tuned)
+  bool tuned = false;
+};
+
+struct mhd_ens {
+  int32_t count = 0;
+  hipStream_t stream = nullptr;
+  std::vector<mhd_ctx*> mem;  // one context per member, on the ensemble stream
+  std::vector<int> grp_of;
+  std::vector<EnsGroup> groups;
+  hipStream_t cap = nullptr;  // capture origin (the caller's stream may be the legacy default stream)
+  hipEvent_t fork = nullptr, t0 = nullptr, t1 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int tune_mode = 1;  // 0: off, 1: in memory, 2: in memory and the cache file
+  std::string tune_path;
+  std::string last_err;
+  int num_cus = 0;
+};
+
+namespace {
+
+int ens_fail(mhd_ens* E, hipError_t e, const char* what) {
+  E->last_err = std::string(what) + ": " + hipGetErrorString(e);
+  return MHD_E_HIP;
+}
+
+// One pass sequence of group G: a step (AB2 coefficients from each member's
+// history) or, with rhs_only, right-hand sides into the members' scratch
+// slots, leaving states and histories unchanged.
+template <typename T>
+void group_launch(mhd_ens* E, EnsGroup& G, const Kern<T>& k, bool rhs_only) {
+  MemberSet ms;
+  ms.n = (int)G.members.size();
+  ms.stride = (int64_t)G.stride;
+  ms.col_scale = G.col_scale;
+  ms.row_scale = G.row_scale;
+  for (int s = 0; s < ms.n; ++s) {
+    const mhd_ctx* mc = E->mem[G.members[s]];
+    ms.gamma[s] = mc->p.gamma;
+    ms.nu[s] = mc->p.nu;
+    ms.eta[s] = mc->p.eta;
+    ms.dt[s] = mc->p.dt;
+    ms.a_cur[s] = mc->first_step ? 1.0 : 1.5;
+    ms.a_prev[s] = mc->first_step ? 0.0 : -0.5;
+  }
+  Engine<T> e(G.lead, k, ms);
+  e.phase_a(e.state());
+  e.phase_b(e.state(), rhs_only ? e.trhs() : nullptr);
+}
+
+// Every group as a parallel branch forked from and joined into `origin` (the
+// ensemble stream, or the capture stream while the graph is recorded).
+int ens_launch(mhd_ens* E, hipStream_t origin, bool rhs_only) {
+  hipError_t e = hipEventRecord(E->fork, origin);
+  for (EnsGroup& G : E->groups) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(G.stream, E->fork, 0);
+    if (e != hipSuccess) break;
+    const void* kv = kern_for(G.lead);
+    if (is_fp32(G.precision)) group_launch(E, G, *static_cast<const Kern<float>*>(kv), rhs_only);
+    else group_launch(E, G, *static_cast<const Kern<double>*>(kv), rhs_only);
+    e = hipEventRecord(G.done, G.stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(origin, G.done, 0);
+  }
+  if (e == hipSuccess) e = hipGetLastError();
+  return e == hipSuccess ? MHD_OK : ens_fail(E, e, "ensemble launch");
+}
+
+std::string tune_key(const EnsGroup& G, int cus) {
+  char b[96];
+  std::snprintf(b, sizeof(b), "%d %d %d %d", G.n, G.precision, (int)G.members.size(), cus);
+  return b;
+}
+
+// Cache lines: "mhd-ens-tune <n> <precision> <members> <CUs> <col_scale> <row_scale>".
+void tune_read(mhd_ens* E) {
+  FILE* f = std::fopen(E->tune_path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    int n, pr, nm, cus;
+    double cs, rs;
+    if (std::sscanf(line, "mhd-ens-tune %d %d %d %d %lf %lf", &n, &pr, &nm, &cus, &cs, &rs) != 6) continue;
+    if (!(cs > 0.0 && cs <= 4.0 && rs > 0.0 && rs <= 4.0)) continue;
+    for (EnsGroup& G : E->groups) {
+      if (G.n == n && G.precision == pr && (int)G.members.size() == nm && E->num_cus == cus) {
+        G.col_scale = cs;
+        G.row_scale = rs;
+        G.tuned = true;
+      }
+    }
+  }
+  std::fclose(f);
+}
+
+void tune_write(mhd_ens* E, const EnsGroup& G) {
+  FILE* f = std::fopen(E->tune_path.c_str(), "a");
+  if (!f) return;  // an unwritable cache only costs a re-tune next time
+  std::fprintf(f, "mhd-ens-tune %s %.4f %.4f\n", tune_key(G, E->num_cus).c_str(), G.col_scale, G.row_scale);
+  std::fclose(f);
+}
+
+// Times right-hand-side evaluations of the whole ensemble (all branches
+// running together), in milliseconds per evaluation.
+int ens_time(mhd_ens* E, int reps, double* ms) {
+  int rc = ens_launch(E, E->stream, true);  // warm-up
+  hipError_t e = hipSuccess;
+  if (rc == MHD_OK) e = hipEventRecord(E->t0, E->stream);
+  for (int r = 0; rc == MHD_OK && e == hipSuccess && r < reps; ++r) rc = ens_launch(E, E->stream, true);
+  if (rc != MHD_OK) return rc;
+  if (e == hipSuccess) e = hipEventRecord(E->t1, E->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(E->t1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, E->t0, E->t1);
+  if (e != hipSuccess) return ens_fail(E, e, "ensemble tuning");
+  *ms = (double)t / reps;
+  return MHD_OK;
+}
+
+// One sweep of coordinate search over the groups: for each untuned group,
+// the persistent-grid scales of its column and row passes that give the
+// fastest whole-ensemble evaluation, the other groups held at their current
+// scales.
+int ens_tune(mhd_ens* E) {
+  static const double kScales[] = {0.25, 0.5, 1.0};
+  for (EnsGroup& G : E->groups) {
+    if (G.tuned) continue;
+    double best = 1e300, bc = 1.0, br = 1.0;
+    for (double cs : kScales) {
+      for (double rs : kScales) {
+        G.col_scale = cs;
+        G.row_scale = rs;
+        double t = 0.0;
+        int rc = ens_time(E, 3, &t);
+        if (rc != MHD_OK) return rc;
+        if (t < best) {
+          best = t;
+          bc = cs;
+          br = rs;
+        }
+      }
+    }
+    G.col_scale = bc;
+    G.row_scale = br;
+    G.tuned = true;
+    if (E->tune_mode == 2) tune_write(E, G);
+  }
+  return MHD_OK;
+}
+
+int ens_capture(mhd_ens* E) {
+  hipError_t e = hipStreamBeginCapture(E->cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return ens_fail(E, e, "hipStreamBeginCapture");
+  int rc = ens_launch(E, E->cap, false);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(E->cap, &g);
+  if (rc != MHD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return ens_fail(E, e, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return ens_fail(E, e, "hipGraphInstantiate");
+  }
+  E->graph = g;
+  E->exec = x;
+  return MHD_OK;
+}
+
+void ens_free(mhd_ens* E) {
+  if (!E) return;
+  if (E->exec) (void)hipGraphExecDestroy(E->exec);
+  if (E->graph) (void)hipGraphDestroy(E->graph);
+  for (EnsGroup& G : E->groups) {
+    if (G.done) (void)hipEventDestroy(G.done);
+    if (G.stream) (void)hipStreamDestroy(G.stream);
+    delete G.lead;
+  }
+  for (mhd_ctx* c : E->mem) mhd_destroy(c);
+  if (E->cap) (void)hipStreamDestroy(E->cap);
+  if (E->fork) (void)hipEventDestroy(E->fork);
+  if (E->t0) (void)hipEventDestroy(E->t0);
+  if (E->t1) (void)hipEventDestroy(E->t1);
+  delete E;
+}
+
+// Group members by (n, precision) in order of first appearance, at most
+// kMaxMem per group; returns the workspace offset of each group.
+size_t ens_plan(const mhd_params* p, int32_t count, std::vector<EnsGroup>& groups, std::vector<int>& grp_of) {
+  groups.clear();
+  grp_of.assign(count, -1);
+  for (int i = 0; i < count; ++i) {
+    int gi = -1;
+    for (int j = 0; j < (int)groups.size(); ++j) {
+      if (groups[j].n == p[i].n && groups[j].precision == p[i].precision && (int)groups[j].members.size() < kMaxMem) {
+        gi = j;
+        break;
+      }
+    }
+    if (gi < 0) {
+      EnsGroup G;
+      G.n = p[i].n;
+      G.precision = p[i].precision;
+      G.stride = align256(mhd_workspace_bytes(&p[i]));
+      groups.push_back(G);
+      gi = (int)groups.size() - 1;
+    }
+    groups[gi].members.push_back(i);
+    grp_of[i] = gi;
+  }
+  size_t total = 0;
+  for (const EnsGroup& G : groups) total += G.stride * G.members.size();
+  return total;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C-ABI
+
+extern "C" {
+
+int mhd_supported_size(int32_t n, int32_t precision) { return size_ok(n, precision) ? 1 : 0; }
+
+int64_t mhd_spectrum_size(int32_t n) {
+  if (n < 1) return 0;
+  return make_geo(n).sc;
+}
+
+int32_t mhd_spectrum_pitch(int32_t n) {
+  if (n < 1) return 0;
+  return make_geo(n).nhp;
+}
+
+size_t mhd_workspace_bytes(const mhd_params* p) {
+  if (validate(p) != MHD_OK) return 0;
+  const size_t ts = is_fp32(p->precision) ? sizeof(float) : sizeof(double);
+  return make_layout(make_geo(p->n), ts).total;
+}
+
+int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream, mhd_ctx** out) {
+  return ctx_create(p, d_workspace, ws_bytes, static_cast<hipStream_t>(hip_stream), out);
+}
+
+int mhd_set_state(mhd_ctx* c, const void* d_fields, int32_t dtype) {
+  if (!c || !d_fields || !dtype_ok(dtype)) return MHD_E_ARG;
+  int rc = with_engine(c, [&](auto& e) {
+    e.forward_real(d_fields, dtype, 8, e.state());
+    e.reset_status();
+    return check_launch(c, "mhd_set_state");
+  });
+  if (rc == MHD_OK) {
+    c->has_state = true;
+    c->first_step = true;
+    c->step = 0;
+    c->t = 0.0;
+  }
+  return rc;
+}
+
+int mhd_get_state(mhd_ctx* c, void* d_fields, int32_t dtype) {
+  if (!c || !d_fields || !dtype_ok(dtype)) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  return with_engine(c, [&](auto& e) {
+    e.inverse_real(e.state(), 8, d_fields, dtype);
+    return check_launch(c, "mhd_get_state");
+  });
+}
+
+int mhd_rhs(mhd_ctx* c, const void* d_in, void* d_out, int32_t dtype) {
+  if (!c || !d_in || !d_out || !dtype_ok(dtype)) return MHD_E_ARG;
+  return with_engine(c, [&](auto& e) {
+    e.forward_real(d_in, dtype, 8, e.tstate());
+    e.phase_a(e.tstate());
+    e.phase_b(e.tstate(), e.trhs());
+    e.inverse_real(e.trhs(), 8, d_out, dtype);
+    return check_launch(c, "mhd_rhs");
+  });
+}
+
+int mhd_step(mhd_ctx* c, int32_t nsteps) {
+  if (!c || nsteps < 0) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  int rc = with_engine(c, [&](auto& e) {
+    for (int s = 0; s < nsteps; ++s) {
+      const bool first = c->first_step && s == 0;
+      e.ms.a_cur[0] = first ? 1.0 : 1.5;
+      e.ms.a_prev[0] = first ? 0.0 : -0.5;
+      e.phase_a(e.state());
+      e.phase_b(e.state(), nullptr);
+    }
+    return check_launch(c, "mhd_step");
+  });
+  if (rc == MHD_OK && nsteps > 0) {
+    c->first_step = false;
+    c->step += nsteps;
+    c->t += nsteps * c->p.dt;
+  }
+  return rc;
+}
+
+int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) { return ctx_diag(c, h); }
 
 int mhd_fft3d(mhd_ctx* c, int32_t dir, const void* d_in, void* d_out) {
   if (!c || !d_in || !d_out || (dir != 1 && dir != -1)) return MHD_E_ARG;
@@ -891,7 +1230,7 @@ double mhd_step_bytes(const mhd_ctx* cc) {
 
 int mhd_destroy(mhd_ctx* c) {
   if (!c) return MHD_OK;
-  for (auto& e : c->ev) hipEventDestroy(e);
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
   delete c;
   return MHD_OK;
 }
@@ -911,5 +1250,168 @@ const char* mhd_status_string(int s) {
 }
 
 const char* mhd_last_error(const mhd_ctx* c) { return c ? c->last_err.c_str() : ""; }
+
+size_t mhd_ens_workspace_bytes(const mhd_params* p, int32_t count) {
+  if (!p || count < 1) return 0;
+  for (int i = 0; i < count; ++i)
+    if (validate(&p[i]) != MHD_OK) return 0;
+  std::vector<EnsGroup> groups;
+  std::vector<int> grp_of;
+  return ens_plan(p, count, groups, grp_of);
+}
+
+int mhd_ens_init(const mhd_params* p, int32_t count, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                 const char* tune_cache_path, mhd_ens** out) {
+  if (!out) return MHD_E_ARG;
+  *out = nullptr;
+  if (!p || count < 1) return MHD_E_ARG;
+  for (int i = 0; i < count; ++i) {
+    const int v = validate(&p[i]);
+    if (v != MHD_OK) return v;
+  }
+  mhd_ens* E = new (std::nothrow) mhd_ens();
+  if (!E) return MHD_E_ARG;
+  E->count = count;
+  E->stream = static_cast<hipStream_t>(hip_stream);
+  const size_t need = ens_plan(p, count, E->groups, E->grp_of);
+  if (!d_workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0) {
+    delete E;
+    return MHD_E_WORKSPACE;
+  }
+  if (!tune_cache_path) E->tune_mode = 1;
+  else if (tune_cache_path[0] == '\0') E->tune_mode = 0;
+  else {
+    E->tune_mode = 2;
+    E->tune_path = tune_cache_path;
+  }
+  E->mem.assign(count, nullptr);
+  char* base = static_cast<char*>(d_workspace);
+  int rc = MHD_OK;
+  for (EnsGroup& G : E->groups) {
+    G.base = base;
+    for (size_t s = 0; s < G.members.size() && rc == MHD_OK; ++s) {
+      const int i = G.members[s];
+      rc = ctx_create(&p[i], base + s * G.stride, G.stride, E->stream, &E->mem[i]);
+    }
+    base += G.stride * G.members.size();
+    if (rc != MHD_OK) break;
+    hipError_t e = hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&G.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      rc = ens_fail(E, e, "mhd_ens_init streams");
+      break;
+    }
+    G.lead = new (std::nothrow) mhd_ctx(*E->mem[G.members[0]]);
+    if (!G.lead) {
+      rc = MHD_E_ARG;
+      break;
+    }
+    G.lead->stream = G.stream;
+  }
+  if (rc == MHD_OK) {
+    hipError_t e = hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&E->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&E->t0);
+    if (e == hipSuccess) e = hipEventCreate(&E->t1);
+    if (e != hipSuccess) rc = ens_fail(E, e, "mhd_ens_init events");
+  }
+  if (rc != MHD_OK) {
+    ens_free(E);
+    return rc;
+  }
+  E->num_cus = E->mem[0]->num_cus;
+  if (E->tune_mode == 0)
+    for (EnsGroup& G : E->groups) G.tuned = true;
+  if (E->tune_mode == 2) tune_read(E);
+  *out = E;
+  return MHD_OK;
+}
+
+int mhd_ens_set_state(mhd_ens* E, int32_t member, const void* d_fields, int32_t dtype) {
+  if (!E || member < 0 || member >= E->count) return MHD_E_ARG;
+  return mhd_set_state(E->mem[member], d_fields, dtype);
+}
+
+int mhd_ens_get_state(mhd_ens* E, int32_t member, void* d_fields, int32_t dtype) {
+  if (!E || member < 0 || member >= E->count) return MHD_E_ARG;
+  return mhd_get_state(E->mem[member], d_fields, dtype);
+}
+
+int mhd_ens_step(mhd_ens* E, int32_t nsteps) {
+  if (!E || nsteps < 0) return MHD_E_ARG;
+  for (mhd_ctx* c : E->mem)
+    if (!c->has_state) return MHD_E_STATE;
+  if (nsteps == 0) return MHD_OK;
+  bool untuned = false;
+  for (const EnsGroup& G : E->groups) untuned = untuned || !G.tuned;
+  if (untuned) {
+    const int rc = ens_tune(E);
+    if (rc != MHD_OK) return rc;
+  }
+  for (int s = 0; s < nsteps; ++s) {
+    bool any_first = false;
+    for (const mhd_ctx* c : E->mem) any_first = any_first || c->first_step;
+    if (any_first) {
+      const int rc = ens_launch(E, E->stream, false);
+      if (rc != MHD_OK) return rc;
+      for (mhd_ctx* c : E->mem) c->first_step = false;
+    } else {
+      if (!E->exec) {
+        const int rc = ens_capture(E);
+        if (rc != MHD_OK) return rc;
+      }
+      const hipError_t e = hipGraphLaunch(E->exec, E->stream);
+      if (e != hipSuccess) return ens_fail(E, e, "hipGraphLaunch");
+    }
+    for (mhd_ctx* c : E->mem) {
+      c->step += 1;
+      c->t += c->p.dt;
+    }
+  }
+  return MHD_OK;
+}
+
+int mhd_ens_diagnostics(mhd_ens* E, mhd_diag* h_out, int32_t* h_status) {
+  if (!E || !h_out) return MHD_E_ARG;
+  int first_bad = MHD_OK;
+  for (int i = 0; i < E->count; ++i) {
+    const int rc = ctx_diag(E->mem[i], &h_out[i]);
+    if (h_status) h_status[i] = rc;
+    if (rc == MHD_E_HIP) {
+      E->last_err = E->mem[i]->last_err;
+      return rc;
+    }
+    if (rc != MHD_OK && first_bad == MHD_OK) first_bad = rc;
+  }
+  return first_bad;
+}
+
+int32_t mhd_ens_num_groups(const mhd_ens* E) { return E ? (int32_t)E->groups.size() : 0; }
+
+int mhd_ens_group_info(const mhd_ens* E, int32_t g, int32_t* n, int32_t* precision, int32_t* members,
+                       double* col_scale, double* row_scale) {
+  if (!E || g < 0 || g >= (int32_t)E->groups.size()) return MHD_E_ARG;
+  const EnsGroup& G = E->groups[g];
+  if (n) *n = G.n;
+  if (precision) *precision = G.precision;
+  if (members) *members = (int32_t)G.members.size();
+  if (col_scale) *col_scale = G.col_scale;
+  if (row_scale) *row_scale = G.row_scale;
+  return MHD_OK;
+}
+
+double mhd_ens_step_bytes(const mhd_ens* E) {
+  if (!E) return 0.0;
+  double b = 0.0;
+  for (const mhd_ctx* c : E->mem) b += mhd_step_bytes(c);
+  return b;
+}
+
+int mhd_ens_destroy(mhd_ens* E) {
+  ens_free(E);
+  return MHD_OK;
+}
+
+const char* mhd_ens_last_error(const mhd_ens* E) { return E ? E->last_err.c_str() : ""; }
 
 }  // extern "C"

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace mhd {
 
@@ -57,6 +58,24 @@ struct Geo {
   int64_t n3;  // real values per field
 };
 
+// Members of an ensemble that share a grid size are run by one launch per
+// pass: member m's arrays sit at byte offset m * mstride from member 0's.
+constexpr int kMaxMem = 64;
+struct Batch {
+  int32_t nmem;     // members in this launch (1 for a single context)
+  int32_t pad;
+  int64_t mstride;  // bytes between consecutive members' workspaces
+};
+
+// Byte arithmetic on a char pointer (not an integer round trip) keeps the
+// pointer's provenance, so the compiler still emits global (not flat) memory
+// instructions through the result.
+template <typename P>
+__host__ __device__ __forceinline__ P* member_ptr(P* p, int m, int64_t stride) {
+  using B = typename std::conditional<std::is_const<P>::value, const char, char>::type;
+  return reinterpret_cast<P*>(reinterpret_cast<B*>(p) + (int64_t)m * stride);
+}
+
 template <typename T>
 struct ColArgs {
   const T* in[kMaxIn];  // complex arrays (interleaved) in the pass's input layout
@@ -66,12 +85,14 @@ struct ColArgs {
   int32_t kind;         // PassKind
   int32_t nout;
   Geo g;
+  Batch bt;
 };
 
-// Forward-z pass that forms the right-hand side (Eqs. MHD1-MHD4 in spectral
-// form) and applies the AB2 update.  Output f is
+// Forward-z pass that forms the right-hand side (Eqs. MHD2-MHD4 in spectral
+// form) and applies the AB2 update.  Output f = 1..7 is
 //   R_f = F_z[A_f] + i kz F_z[Z_f] - eta |k|^2 B^_f (f = 4, 5, 6),
-// with A_f, Z_f combinations of the y-transformed fluxes; R_rho = -i k.m^.
+// with A_f, Z_f combinations of the y-transformed fluxes.  The density pass
+// (Eq. MHD1, R_rho = -i k.m^) takes the same arguments.
 template <typename T>
 struct RhsArgs {
   const T* flux[kMaxIn];  // I_z flux slots
@@ -81,8 +102,10 @@ struct RhsArgs {
   T* rprev;               // compact [8][sc] (R^{n-1}, overwritten with R^n)
   T* rout;                // if non-null: store R here, leave state/rprev untouched
   const T* tw;
-  double dt, a_cur, a_prev, eta;
   Geo g;
+  Batch bt;
+  // per member: time step, AB2 coefficients of R^n and R^{n-1}, diffusivity
+  double dt[kMaxMem], a_cur[kMaxMem], a_prev[kMaxMem], eta[kMaxMem];
 };
 
 enum RowMode { RM_XA = 0, RM_XB = 1, RM_XFWD_REAL = 2, RM_XINV_REAL = 3, RM_XDIAG = 4 };
@@ -97,11 +120,12 @@ struct RowArgs {
   void* real_out;           // [nf][n^3] real rows (RM_XINV_REAL)
   int32_t real_dtype;       // 0 = double, 1 = float
   int32_t nf;               // fields of an I/O pass
-  double gamma, nu, eta;
-  double* partials;         // per-block records (RM_XDIAG)
+  double* partials;         // per-block records (RM_XDIAG, single member)
   unsigned* status;         // [0] max CFL speed (float bits), [1] non-finite count (RM_XB)
   const T* tw;
   Geo g;
+  Batch bt;
+  double gamma[kMaxMem], nu[kMaxMem], eta[kMaxMem];  // per member
 };
 
 }  // namespace mhd

@@ -109,7 +109,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   // columns (kx >= NH) are never read or written
   const int ncols = zpass ? NBB * NHP : NH;
   const int ntiles = (ncols + C - 1) / C;
-  const int total = ntiles * (zpass ? 1 : N) * a.nout;  // < 2^31 for every supported size
+  const int per_mem = ntiles * (zpass ? 1 : N) * a.nout;
+  const int total = per_mem * a.bt.nmem;  // < 2^31 for every supported size and member count
   // strides (complex elements) of the input and output layouts
   int64_t os_in, ls_in, os_out, ls_out;
   switch (a.kind) {
@@ -122,12 +123,14 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
   auto col_ok = [&](int col) { return col < ncols && (!zpass || col - (col / NHP) * NHP < NH); };
 
   struct Item {
-    int f, outer, c0;
+    int m, f, outer, c0;
   };
   auto decode = [&](int item) {
     Item it;
-    const int t = item / a.nout;
-    it.f = item - t * a.nout;
+    it.m = item / per_mem;
+    const int rest = item - it.m * per_mem;
+    const int t = rest / a.nout;
+    it.f = rest - t * a.nout;
     it.outer = t / ntiles;
     it.c0 = (t - it.outer * ntiles) * C;
     return it;
@@ -151,7 +154,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
           const int64_t idx = base_in + l * ls_in + c;
 #pragma unroll
           for (int t = 0; t < MAXT; ++t)
-            if (t < sp.nterms) px[t][i][r] = ld(a.in[sp.t[t].src], idx);
+            if (t < sp.nterms) px[t][i][r] = ld(member_ptr(a.in[sp.t[t].src], it.m, a.bt.mstride), idx);
         }
       }
     }
@@ -211,7 +214,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
       }
     }
     __syncthreads();  // the previous item's last pass is done reading the tile
-    T* out = a.out[it.f];
+    T* out = member_ptr(a.out[it.f], it.m, a.bt.mstride);
     const int64_t base_out = it.outer * os_out + it.c0;
     auto store = [&](int, int, int c, int q, cx<T> val) {
       if (!col_ok(it.c0 + c)) return;
@@ -231,7 +234,8 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
 }
 
 // ------------------------------------------------------------------ k_zfwd_rhs
-// Flat grid over (column tile of (ky, kx), output field f = 0..7), field fastest.
+// Flat grid over (member, column tile of (ky, kx), output field f = 1..7),
+// field fastest.
 template <typename T, int N, bool MX>
 __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
   using PL = PlanOf<N, MX>;
@@ -242,45 +246,37 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
-  const TileField tf = tile_field(8);
-  const int f = tf.field;
-  const int c0 = tf.tile * C;
+  // fields 1..7; R_rho is formed by its own pass before this one, because
+  // this pass overwrites m^ (which R_rho = -i k . m^ reads) with its next level
+  const TileField tf = tile_field(7);
+  const int f = tf.field + 1;
+  constexpr int ZT = (NCOLS + C - 1) / C;  // column tiles per member
+  const int mem = tf.tile / ZT;
+  const int c0 = (tf.tile - mem * ZT) * C;
   const int64_t sc = a.g.sc;
   const int64_t LS = NCOLS;  // row stride of I_z (z) and of compact (kz)
-  const T dt = T(a.dt), ac = T(a.a_cur), ap = T(a.a_prev);
-  const bool use_prev = a.a_prev != 0.0;
+  const T dt = T(a.dt[mem]), ac = T(a.a_cur[mem]), ap = T(a.a_prev[mem]);
+  const bool use_prev = a.a_prev[mem] != 0.0;
+  const int64_t ms = a.bt.mstride;
+  T* const state = member_ptr(a.state, mem, ms);
+  T* const rprev = member_ptr(a.rprev, mem, ms);
+  T* const rout = a.rout ? member_ptr(a.rout, mem, ms) : nullptr;
 
   // R_f -> store, or the AB2 update U += dt (a_cur R^n + a_prev R^{n-1}), R^{n-1} <- R^n
   auto finish = [&](int64_t idx, cx<T> R) {
-    if (a.rout) {
-      st(a.rout, idx, R);
+    if (rout) {
+      st(rout, idx, R);
     } else {
-      cx<T> u = ld(a.state, idx);
+      cx<T> u = ld(state, idx);
       cx<T> inc = cscale(R, ac);
-      if (use_prev) inc = cadd(inc, cscale(ld(a.rprev, idx), ap));
+      if (use_prev) inc = cadd(inc, cscale(ld(rprev, idx), ap));
       u.x += dt * inc.x;
       u.y += dt * inc.y;
-      st(a.state, idx, u);
-      st(a.rprev, idx, R);
+      st(state, idx, u);
+      st(rprev, idx, R);
     }
   };
 
-  if (f == 0) {
-    // MHD1: R_rho = -i k . m^ (state fields 1..3, already band-limited)
-    for (int e = tid; e < NBB * C; e += kThreads) {
-      const int l = e / C, c = e - (e / C) * C, col = c0 + c;
-      const int kx = col - (col / NHP) * NHP;
-      if (col < NCOLS && kx < NH) {
-        const int kz = band_k<N>(l), ky = band_k<N>(col / NHP);
-        const int64_t idx = (int64_t)l * LS + col;
-        const cx<T> mx = ld(a.state, 1 * sc + idx), my = ld(a.state, 2 * sc + idx), mz = ld(a.state, 3 * sc + idx);
-        const T dx = T(kx) * mx.x + T(ky) * my.x + T(kz) * mz.x;
-        const T dy = T(kx) * mx.y + T(ky) * my.y + T(kz) * mz.y;
-        finish(idx, mk<T>(dy, -dx));  // -i (dx + i dy)
-      }
-    }
-    return;
-  }
   load_twiddles<T, N>(stw, a.tw, tid);
   cx<T> acc[LP::CNT][LP::R];
 #pragma unroll
@@ -293,8 +289,8 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
     const int nt = sp.nterms;
     if (nt == 0) continue;           // uniform across the block
     if (grp == 1) __syncthreads();   // the LDS tile is about to be rewritten
-    const T* p0 = a.flux[sp.t[0].src];
-    const T* p1 = nt > 1 ? a.flux[sp.t[1].src] : p0;
+    const T* p0 = member_ptr(a.flux[sp.t[0].src], mem, ms);
+    const T* p1 = nt > 1 ? member_ptr(a.flux[sp.t[1].src], mem, ms) : p0;
     auto load = [&](int c, int q) -> cx<T> {
       const int col = c0 + c;
       cx<T> v = mk<T>(0, 0);
@@ -335,19 +331,18 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
     fft_reg<T, PL, C, kThreads, C, 1, -1>(tile, stw, tid, C, load, store);
   }
   // epilogue over this thread's last-pass positions: resistive term, update
-  const T eta = T(a.eta);
+  const T eta = T(a.eta[mem]);
 #pragma unroll
   for (int i = 0; i < LP::CNT; ++i) {
-    const int w = tid + i * kThreads;
-    const int c = w % C, j = w / C;
-    if (LP::TOT % kThreads != 0 && w >= LP::TOT) continue;
-    const int col = c0 + c;
-    const int kx = col - (col / NHP) * NHP;
-    if (col >= NCOLS || kx >= NH) continue;
-    const int ky = band_k<N>(col / NHP);
 #pragma unroll
     for (int r = 0; r < LP::R; ++r) {
-      const int l = pos_band<N>(j + r * LP::NBF);
+      int c, q;
+      if (!last_slot<PL, C, kThreads, 0>(tid, i, r, c, q)) continue;
+      const int col = c0 + c;
+      const int kx = col - (col / NHP) * NHP;
+      if (col >= NCOLS || kx >= NH) continue;
+      const int ky = band_k<N>(col / NHP);
+      const int l = pos_band<N>(q);
       if (l < 0) continue;
       const int64_t idx = f * sc + (int64_t)l * LS + col;
       cx<T> R = acc[i][r];
@@ -355,7 +350,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
         // MHD4 resistive term: - eta |k|^2 B^
         const int kz = band_k<N>(l);
         const T k2 = T(kx * kx + ky * ky + kz * kz);
-        const cx<T> b = ld(a.state, idx);
+        const cx<T> b = ld(state, idx);
         R.x -= eta * k2 * b.x;
         R.y -= eta * k2 * b.y;
       }
@@ -401,6 +396,24 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s,
 // spectral-input modes the global loads of the next row pair's first FFT pass
 // are issued right after the current pair's first pass, so they are in flight
 // during the current pair's LDS passes, pointwise work and stores.
+// Fold a workgroup's CFL speed and non-finite count into a member's status
+// words: an unsigned max over the bit patterns of non-negative floats orders
+// them like the floats (NaN sorts above every finite value), and integer adds
+// commute, so the result does not depend on block order.  Block-uniform call.
+template <typename T>
+__device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status) {
+  __shared__ double s_red[kThreads];
+  const int tid = threadIdx.x;
+  const double cfl_b = block_reduce(double(cfl), true, s_red, tid);
+  const double bad_b = block_reduce(double(bad), false, s_red, tid);
+  if (tid == 0) {
+    const float cf = float(cfl_b);
+    const unsigned bits = (cf != cf) ? 0x7fc00000u : (cf > 0.f ? __float_as_uint(cf) : 0u);
+    atomicMax(&status[0], bits);
+    if (bad_b > 0) atomicAdd(&status[1], (unsigned)bad_b);
+  }
+}
+
 template <typename T, int N, int MODE, bool MX>
 __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
   using PL = PlanOf<N, MX>;
@@ -415,7 +428,8 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
-  const int64_t nitems = (int64_t)N * N / 2;
+  const int64_t rows_per_mem = (int64_t)N * N / 2;
+  const int64_t nitems = rows_per_mem * a.bt.nmem;
   const int nin = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NIN;
   const int nout = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NOUT;
   load_twiddles<T, N>(stw, a.tw, tid);
@@ -428,14 +442,16 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
   constexpr int RH = FP::R / 2;
   cx<T> p0[FP::CNT][RH], p1[FP::CNT][RH];
   auto issue = [&](int64_t item) {
-    const int64_t row0 = 2 * item;
+    const int mi = (int)(item / rows_per_mem);
+    const int64_t row0 = 2 * (item - mi * rows_per_mem);
+    const T* in0 = member_ptr(a.in0, mi, a.bt.mstride);
 #pragma unroll
     for (int i = 0; i < FP::CNT; ++i) {
       const int w = tid + i * kThreads;
       int b, j;
       lane_map<NB, FP::NBF, 1>(w, b, j);
       const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && b < nin;
-      const T* src = a.in0 + 2 * b * a.in_stride;
+      const T* src = in0 + 2 * b * a.in_stride;
 #pragma unroll
       for (int r = 0; r < RH; ++r) {
         const int q = j + r * FP::NBF;
@@ -457,9 +473,21 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
   if constexpr (SPEC_IN) {
     if (item < nitems) issue(item);
   }
+  int cur_m = -1;  // member whose CFL / non-finite status is being accumulated
   for (; item < nitems; item += gridDim.x) {
-    const int64_t row0 = 2 * item;  // flattened row index z*N + y of the first row
-    __syncthreads();                // the previous row pair is done with the LDS
+    const int mem = (int)(item / rows_per_mem);
+    const int64_t row0 = 2 * (item - mem * rows_per_mem);  // flattened row z*N + y of the first row
+    if constexpr (MODE == RM_XB) {
+      if (mem != cur_m) {  // uniform across the workgroup
+        if (cur_m >= 0) {
+          flush_status(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
+          cfl = T(0);
+          bad = 0;
+        }
+        cur_m = mem;
+      }
+    }
+    __syncthreads();  // the previous row pair is done with the LDS
     if constexpr (!SPEC_IN) {
       // real rows -> packed complex row0 + i row1
       for (int e = tid; e < nin * N; e += kThreads) {
@@ -486,7 +514,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
         int b, j;
         lane_map<NB, FP::NBF, 1>(w, b, j);
         const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && b < nin;
-        const T* src = a.in0 + 2 * b * a.in_stride;
+        const T* src = member_ptr(a.in0, mem, a.bt.mstride) + 2 * b * a.in_stride;
 #pragma unroll
         for (int r = 0; r < FP::R; ++r) {
           const int q = j + r * FP::NBF;
@@ -548,7 +576,8 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
       // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8 S_xx, 9 S_yy, 10 S_xy, 11 S_xz,
       // 12 S_yz, 13-15 J.  Outputs: 0 Pi_xx, 1 Pi_yy, 2 Pi_zz, 3 Pi_xy,
       // 4 Pi_xz, 5 Pi_yz, 6-8 F^E, 9-11 e = u x B.
-      const T gm1 = T(a.gamma - 1.0), gam = T(a.gamma), two_nu = T(2.0 * a.nu), eta = T(a.eta);
+      const T gm1 = T(a.gamma[mem] - 1.0), gam = T(a.gamma[mem]), two_nu = T(2.0 * a.nu[mem]),
+              eta = T(a.eta[mem]);
       for (int x = tid; x < N; x += kThreads) {
         cx<T> v[16];
 #pragma unroll
@@ -606,7 +635,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
 
     if constexpr (MODE == RM_XDIAG) {
       // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8-10 J, 11 div B.
-      const double gm1 = a.gamma - 1.0, gam = a.gamma;
+      const double gm1 = a.gamma[mem] - 1.0, gam = a.gamma[mem];
       for (int x = tid; x < N; x += kThreads) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -645,7 +674,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
       __syncthreads();
       lds_fft<T, PL, NB, kThreads, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
       // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
-      T* out0 = a.out0;
+      T* out0 = member_ptr(a.out0, mem, a.bt.mstride);
       const int64_t ost = a.out_stride;
       for (int e = tid; e < nout * NH; e += kThreads) {
         const int fld = e / NH, k = e - (e / NH) * NH;
@@ -661,19 +690,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
   }
 
   if constexpr (MODE == RM_XB) {
-    // Fold the workgroup's CFL speed and non-finite count into the status
-    // words: an unsigned max over the bit patterns of non-negative floats
-    // orders them like the floats (NaN sorts above every finite value), and
-    // integer adds commute, so the result does not depend on block order.
-    __shared__ double s_red[kThreads];
-    const double cfl_b = block_reduce(double(cfl), true, s_red, tid);
-    const double bad_b = block_reduce(double(bad), false, s_red, tid);
-    if (tid == 0) {
-      const float cf = float(cfl_b);
-      const unsigned bits = (cf != cf) ? 0x7fc00000u : (cf > 0.f ? __float_as_uint(cf) : 0u);
-      atomicMax(&a.status[0], bits);
-      if (bad_b > 0) atomicAdd(&a.status[1], (unsigned)bad_b);
-    }
+    if (cur_m >= 0) flush_status(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
   }
   if constexpr (MODE == RM_XDIAG) {
     __shared__ double s_red[kThreads];

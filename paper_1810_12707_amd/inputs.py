@@ -244,3 +244,25 @@ def config_dynamo512(n: int = 512) -> Case:
 def config_ot1024(n: int = 1024) -> Case:
     """1024^3 Orszag-Tang-type start, nu = eta = 5e-4, 50 steps."""
     return orszag_tang(n, name=f"ot{n}")
+
+
+# Stream of the ensemble's per-run diffusivities (independent of the field seeds).
+ENSEMBLE_PARAM_SEED = 0x5EED_0E15
+
+
+def ensemble_member(i: int, n: int, steps: int = 500, mach: float = 0.3, b_rms: float = 0.1) -> Case:
+    """Run i of the batched ensemble: random-phase turbulence (as
+    random_turbulence) from seed i, with nu = eta = 10^(-3 + v), v uniform in
+    (0, 1] (log-uniform in [1e-3, 1e-2]), dt from the CFL condition."""
+    v = float(uniform01(ENSEMBLE_PARAM_SEED, np.array([i]))[0])
+    nu = 10.0 ** (-3.0 + v)
+    return random_turbulence(n, nu=nu, eta=nu, steps=steps, mach=mach, b_rms=b_rms,
+                             seeds=(i, 1000 + i, 2000 + i), name=f"ens{i}_n{n}")
+
+
+def config_ensemble(count: int = 64, sizes=(32, 64, 96, 128), steps: int = 500) -> list:
+    """The batched ensemble: `count` runs, sizes in equal consecutive blocks
+    (16 each of 32^3, 64^3, 96^3, 128^3 by default: 52.4 M points), seeds
+    0..count-1, FP32, 500 steps."""
+    per = max(1, count // len(sizes))
+    return [ensemble_member(i, sizes[min(i // per, len(sizes) - 1)], steps) for i in range(count)]

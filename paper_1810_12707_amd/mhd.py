@@ -26,9 +26,13 @@ EXPORTED = (
     "mhd_supported_size", "mhd_workspace_bytes", "mhd_init", "mhd_set_state", "mhd_get_state",
     "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_spectrum_pitch", "mhd_destroy",
     "mhd_status_string", "mhd_last_error", "mhd_profile", "mhd_profile_read", "mhd_step_bytes",
+    "mhd_ens_workspace_bytes", "mhd_ens_init", "mhd_ens_set_state", "mhd_ens_get_state", "mhd_ens_step",
+    "mhd_ens_diagnostics", "mhd_ens_num_groups", "mhd_ens_group_info", "mhd_ens_step_bytes", "mhd_ens_destroy",
+    "mhd_ens_last_error",
 )
 
-PASS_NAMES = ("zinv_a", "yinv_a", "xa", "yfwd_a", "zfwd_a", "zinv_b", "yinv_b", "xb", "yfwd_b", "zrhs", "reduce")
+PASS_NAMES = ("zinv_a", "yinv_a", "xa", "yfwd_a", "zfwd_a", "zinv_b", "yinv_b", "xb", "yfwd_b", "zrhs", "rho",
+              "reduce")
 
 
 class mhd_params(ctypes.Structure):
@@ -102,8 +106,27 @@ def lib() -> ctypes.CDLL:
         L.mhd_profile_read.restype = ctypes.c_int
         L.mhd_step_bytes.argtypes = [vp]
         L.mhd_step_bytes.restype = ctypes.c_double
+        i32 = ctypes.c_int32
+        L.mhd_ens_workspace_bytes.argtypes = [P, i32]
+        L.mhd_ens_workspace_bytes.restype = ctypes.c_size_t
+        L.mhd_ens_init.argtypes = [P, i32, vp, ctypes.c_size_t, vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.mhd_ens_set_state.argtypes = [vp, i32, vp, i32]
+        L.mhd_ens_get_state.argtypes = [vp, i32, vp, i32]
+        L.mhd_ens_step.argtypes = [vp, i32]
+        L.mhd_ens_diagnostics.argtypes = [vp, ctypes.POINTER(mhd_diag), ctypes.POINTER(i32)]
+        L.mhd_ens_num_groups.argtypes = [vp]
+        L.mhd_ens_num_groups.restype = i32
+        ip = ctypes.POINTER(i32)
+        L.mhd_ens_group_info.argtypes = [vp, i32, ip, ip, ip, dp, dp]
+        L.mhd_ens_step_bytes.argtypes = [vp]
+        L.mhd_ens_step_bytes.restype = ctypes.c_double
+        L.mhd_ens_destroy.argtypes = [vp]
+        L.mhd_ens_last_error.argtypes = [vp]
+        L.mhd_ens_last_error.restype = ctypes.c_char_p
         for name in ("mhd_supported_size", "mhd_init", "mhd_set_state", "mhd_get_state", "mhd_rhs",
-                     "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_destroy"):
+                     "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_destroy", "mhd_ens_init",
+                     "mhd_ens_set_state", "mhd_ens_get_state", "mhd_ens_step", "mhd_ens_diagnostics",
+                     "mhd_ens_group_info", "mhd_ens_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -222,7 +245,80 @@ def mhd_destroy(ctx):
     lib().mhd_destroy(ctx)
 
 
-# ---------------------------------------------------------------- convenience owner
+def _rc_ens(rc: int, what: str, ens=None):
+    if rc != MHD_OK:
+        msg = what
+        if ens is not None and rc == MHD_E_HIP:
+            msg += " [" + lib().mhd_ens_last_error(ens).decode() + "]"
+        raise MHDError(rc, msg)
+
+
+def _params_array(plist):
+    arr = (mhd_params * len(plist))()
+    for i, p in enumerate(plist):
+        arr[i] = p
+    return arr
+
+
+def mhd_ens_workspace_bytes(plist) -> int:
+    return int(lib().mhd_ens_workspace_bytes(_params_array(plist), len(plist)))
+
+
+def mhd_ens_init(plist, workspace, stream_handle: int, tune_cache_path=None):
+    """workspace: uint8 CUDA tensor of >= mhd_ens_workspace_bytes(plist) bytes, 256-byte aligned.
+    tune_cache_path: None (tune, keep in memory), "" (no tuning) or a file path."""
+    ens = ctypes.c_void_p()
+    path = None if tune_cache_path is None else str(tune_cache_path).encode()
+    rc = lib().mhd_ens_init(_params_array(plist), len(plist), ctypes.c_void_p(workspace.data_ptr()),
+                            workspace.numel(), ctypes.c_void_p(stream_handle), path, ctypes.byref(ens))
+    _rc_ens(rc, "mhd_ens_init")
+    return ens
+
+
+def mhd_ens_set_state(ens, member: int, fields):
+    _rc_ens(lib().mhd_ens_set_state(ens, int(member), ctypes.c_void_p(fields.data_ptr()), _dtype_code(fields)),
+            "mhd_ens_set_state", ens)
+
+
+def mhd_ens_get_state(ens, member: int, out):
+    _rc_ens(lib().mhd_ens_get_state(ens, int(member), ctypes.c_void_p(out.data_ptr()), _dtype_code(out)),
+            "mhd_ens_get_state", ens)
+
+
+def mhd_ens_step(ens, nsteps: int):
+    _rc_ens(lib().mhd_ens_step(ens, int(nsteps)), "mhd_ens_step", ens)
+
+
+def mhd_ens_diagnostics(ens, count: int) -> tuple[int, list[int], list[dict]]:
+    d = (mhd_diag * count)()
+    st = (ctypes.c_int32 * count)()
+    rc = lib().mhd_ens_diagnostics(ens, d, st)
+    if rc not in (MHD_OK, MHD_E_NONFINITE, MHD_E_CFL):
+        _rc_ens(rc, "mhd_ens_diagnostics", ens)
+    return rc, list(st), [d[i].as_dict() for i in range(count)]
+
+
+def mhd_ens_num_groups(ens) -> int:
+    return int(lib().mhd_ens_num_groups(ens))
+
+
+def mhd_ens_group_info(ens, g: int) -> dict:
+    n, pr, nm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    cs, rs = ctypes.c_double(), ctypes.c_double()
+    _rc_ens(lib().mhd_ens_group_info(ens, int(g), ctypes.byref(n), ctypes.byref(pr), ctypes.byref(nm),
+                                     ctypes.byref(cs), ctypes.byref(rs)), "mhd_ens_group_info", ens)
+    return {"n": n.value, "precision": pr.value, "members": nm.value, "col_scale": cs.value, "row_scale": rs.value}
+
+
+def mhd_ens_step_bytes(ens) -> float:
+    return float(lib().mhd_ens_step_bytes(ens))
+
+
+def mhd_ens_destroy(ens):
+    lib().mhd_ens_destroy(ens)
+
+
+# ---------------------------------------------------------------- convenience owners
 
 class Solver:
     """Owns one context, its workspace tensor and the stream it runs on."""
@@ -306,6 +402,71 @@ class Solver:
         if getattr(self, "ctx", None) is not None:
             mhd_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Owns one ensemble: its workspace tensor, the stream it runs on and the
+    member parameters (a list of dicts with keys n, precision, gamma, nu, eta,
+    dt, cfl, flags; missing keys take make_params' defaults)."""
+
+    def __init__(self, members, device="cuda:0", stream=None, tune_cache=None):
+        import torch
+
+        self.torch = torch
+        codes = {"fp64": MHD_FP64, "fp32": MHD_FP32, "mixed": MHD_MIXED}
+        self.plist = []
+        for m in members:
+            m = dict(m)
+            pr = m.pop("precision", MHD_FP32)
+            m["precision"] = codes[pr] if isinstance(pr, str) else int(pr)
+            self.plist.append(make_params(**m))
+        self.count = len(self.plist)
+        nbytes = mhd_ens_workspace_bytes(self.plist)
+        if nbytes == 0:
+            raise MHDError(MHD_E_ARG, "mhd_ens_workspace_bytes")
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws = self.workspace[off:off + nbytes]
+        self.ens = mhd_ens_init(self.plist, self._ws, self.stream.cuda_stream, tune_cache)
+
+    def n_of(self, member: int) -> int:
+        return int(self.plist[member].n)
+
+    def set_state(self, member: int, U):
+        _check_fields(U, self.n_of(member))
+        mhd_ens_set_state(self.ens, member, U)
+
+    def get_state(self, member: int, dtype=None):
+        n = self.n_of(member)
+        out = self.torch.empty((8, n, n, n), dtype=dtype or self.torch.float64, device=self.device)
+        mhd_ens_get_state(self.ens, member, out)
+        return out
+
+    def step(self, nsteps=1):
+        mhd_ens_step(self.ens, nsteps)
+
+    def diagnostics(self):
+        return mhd_ens_diagnostics(self.ens, self.count)
+
+    def groups(self) -> list[dict]:
+        return [mhd_ens_group_info(self.ens, g) for g in range(mhd_ens_num_groups(self.ens))]
+
+    @property
+    def step_bytes(self) -> float:
+        return mhd_ens_step_bytes(self.ens)
+
+    def close(self):
+        if getattr(self, "ens", None) is not None:
+            mhd_ens_destroy(self.ens)
+            self.ens = None
 
     def __del__(self):
         try:

@@ -99,3 +99,44 @@ def test_null_context_calls(M):
     assert L.mhd_diagnostics(None, None) == M.MHD_E_ARG
     assert L.mhd_fft3d(None, 1, None, None) == M.MHD_E_ARG
     assert L.mhd_last_error(None) == b""
+    assert L.mhd_ens_step(None, 1) == M.MHD_E_ARG
+    assert L.mhd_ens_set_state(None, 0, None, 0) == M.MHD_E_ARG
+    assert L.mhd_ens_diagnostics(None, None, None) == M.MHD_E_ARG
+    assert L.mhd_ens_num_groups(None) == 0
+    assert L.mhd_ens_step_bytes(None) == 0.0
+    assert L.mhd_ens_last_error(None) == b""
+    assert L.mhd_ens_destroy(None) == M.MHD_OK
+
+
+def test_ensemble_workspace_and_rejections(M):
+    L = M.lib()
+
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    plist = [M.make_params(32), M.make_params(64), M.make_params(32, M.MHD_FP64), M.make_params(32)]
+    need = M.mhd_ens_workspace_bytes(plist)
+    assert need == sum(a256(M.mhd_workspace_bytes(p)) for p in plist)
+    # one invalid member invalidates the ensemble
+    bad = list(plist) + [M.make_params(20)]
+    assert M.mhd_ens_workspace_bytes(bad) == 0
+    arr = M._params_array(plist)
+    ens = ctypes.c_void_p()
+    assert L.mhd_ens_workspace_bytes(arr, 0) == 0
+    assert L.mhd_ens_init(arr, 0, ctypes.c_void_p(4096), need, None, None, ctypes.byref(ens)) == M.MHD_E_ARG
+    assert L.mhd_ens_init(arr, len(plist), ctypes.c_void_p(4096), need, None, None, None) == M.MHD_E_ARG
+    assert L.mhd_ens_init(M._params_array(bad), len(bad), ctypes.c_void_p(4096), need, None, None,
+                          ctypes.byref(ens)) == M.MHD_E_SIZE
+    assert L.mhd_ens_init(arr, len(plist), ctypes.c_void_p(4096), need - 1, None, None,
+                          ctypes.byref(ens)) == M.MHD_E_WORKSPACE
+    assert L.mhd_ens_init(arr, len(plist), ctypes.c_void_p(4096 + 64), need, None, None,
+                          ctypes.byref(ens)) == M.MHD_E_WORKSPACE
+    assert L.mhd_ens_init(arr, len(plist), None, need, None, None, ctypes.byref(ens)) == M.MHD_E_WORKSPACE
+
+
+def test_pass_names_match_header(M):
+    src = open(os.path.join(ROOT, "include", "mhd.h")).read()
+    body = re.search(r"enum\s*\{\s*(MHD_PASS_ZINV_A.*?)\}", src, flags=re.S).group(1)
+    names = [t.split("=")[0].strip() for t in body.replace("\n", " ").split(",") if t.strip()]
+    assert names[-1] == "MHD_PASS_COUNT"
+    assert [n[len("MHD_PASS_"):].lower() for n in names[:-1]] == list(M.PASS_NAMES)

@@ -1,0 +1,179 @@
+"""Batched ensembles through the C-ABI (mhd_ens_*).
+
+Each member of an ensemble runs the same arithmetic as a single context with
+its parameters, so its state must equal a solo run's bit for bit -- through
+the eager first (Euler) step, the graph-replayed AB2 steps, a mid-run reset of
+one member and a non-finite value planted in another.  One ensemble is also
+held to the oracle directly (FP32 bound after 10 steps: 1e-5 per field).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1810_12707_amd import inputs as I
+from tests.gpu_helpers import log, per_field_rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# (n, precision, seed): several sizes (24 has a radix-3 stage), all three
+# precisions, two members sharing a group with different nu/eta/dt
+MEMBERS = [(16, "fp32", 0), (24, "fp32", 1), (16, "fp32", 2), (32, "fp32", 3), (24, "fp64", 4), (16, "mixed", 5),
+           (16, "fp32", 6)]
+
+
+def case(n, seed):
+    return I.ensemble_member(seed, n)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda:0", dtype=torch.float64)
+
+
+def member_dict(n, prec, c):
+    return {"n": n, "precision": prec, "gamma": c.gamma, "nu": c.nu, "eta": c.eta, "dt": c.dt}
+
+
+def make_ensemble(spec, cases, tune_cache=None):
+    from paper_1810_12707_amd.mhd import Ensemble
+
+    return Ensemble([member_dict(n, p, c) for (n, p, _), c in zip(spec, cases)], tune_cache=tune_cache)
+
+
+def make_solo(n, prec, c):
+    from paper_1810_12707_amd.mhd import Solver
+
+    return Solver(n, precision=prec, gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt)
+
+
+def states_equal(a, b):
+    return bool(torch.equal(a, b))
+
+
+def test_members_match_solo_runs_bitwise():
+    log("[ens] members vs solo runs, bitwise")
+    cases = [case(n, s) for n, _, s in MEMBERS]
+    E = make_ensemble(MEMBERS, cases)
+    groups = E.groups()
+    log("  groups", groups)
+    assert sorted((g["n"], g["precision"], g["members"]) for g in groups) == [(16, 1, 3), (16, 2, 1), (24, 0, 1),
+                                                                              (24, 1, 1), (32, 1, 1)]
+    solos = []
+    for i, ((n, p, _), c) in enumerate(zip(MEMBERS, cases)):
+        E.set_state(i, dev(c.U))
+        S = make_solo(n, p, c)
+        S.set_state(dev(c.U))
+        solos.append(S)
+    E.step(1)   # Euler start, eager
+    E.step(5)   # AB2 steps, graph replays
+    for S in solos:
+        S.step(1)
+        S.step(5)
+    rc, st, diags = E.diagnostics()
+    log("  status", st)
+    assert rc == 0 and st == [0] * len(MEMBERS)
+    for i, S in enumerate(solos):
+        a = E.get_state(i)
+        b = S.get_state()
+        assert states_equal(a, b), f"member {i} differs from its solo run"
+        rs, ds = S.diagnostics()
+        assert rs == 0
+        assert diags[i]["step"] == 6 and ds["step"] == 6
+        for k in ("e_kin", "e_mag", "e_tot", "h_cross", "h_mag", "divb_rms", "dt_cfl"):
+            assert diags[i][k] == ds[k], (i, k)
+        S.close()
+    E.close()
+
+
+def test_reset_and_poisoned_member():
+    log("[ens] reset one member, poison another")
+    spec = [(16, "fp32", 10), (16, "fp32", 11), (24, "fp32", 12), (16, "fp32", 13)]
+    cases = [case(n, s) for n, _, s in spec]
+    E = make_ensemble(spec, cases)
+    solos = [make_solo(n, p, c) for (n, p, _), c in zip(spec, cases)]
+    for i, c in enumerate(cases):
+        E.set_state(i, dev(c.U))
+        solos[i].set_state(dev(c.U))
+    E.step(3)
+    for S in solos:
+        S.step(3)
+    # member 2 restarts from a new state (its next step is Euler, the others' AB2)
+    fresh = case(24, 99).U
+    E.set_state(2, dev(fresh))
+    solos[2].set_state(dev(fresh))
+    # member 1 gets a NaN planted in its energy field
+    bad = dev(cases[1].U).clone()
+    bad[7, 3, 4, 5] = float("nan")
+    E.set_state(1, bad)
+    E.step(4)
+    for i, S in enumerate(solos):
+        if i != 1:
+            S.step(4)
+    rc, st, _ = E.diagnostics()
+    log("  status", st)
+    assert st[1] == -5  # MHD_E_NONFINITE
+    assert rc == -5
+    assert st[0] == 0 and st[2] == 0 and st[3] == 0
+    for i in (0, 2, 3):
+        assert states_equal(E.get_state(i), solos[i].get_state()), f"member {i} differs from its solo run"
+    for S in solos:
+        S.close()
+    E.close()
+
+
+def test_ensemble_matches_oracle_ten_steps():
+    log("[ens] ten steps vs oracle")
+    spec = [(16, "fp32", 20), (24, "fp32", 21), (16, "fp32", 22)]
+    cases = [case(n, s) for n, _, s in spec]
+    E = make_ensemble(spec, cases)
+    for i, c in enumerate(cases):
+        E.set_state(i, dev(c.U))
+    E.step(10)
+    for i, c in enumerate(cases):
+        ref = O.run(c.U, 10, c.dt, c.gamma, c.nu, c.eta)
+        errs = per_field_rel_l2(E.get_state(i).cpu().numpy(), ref)
+        log(f"  member {i} n={c.n} nu={c.nu:.3e}", ["%.2e" % e for e in errs])
+        assert max(errs) <= 1e-5
+    E.close()
+
+
+def test_group_split_above_64_members():
+    log("[ens] 65 members of one size")
+    spec = [(8, "fp32", s) for s in range(65)]
+    cases = [case(8, s) for s in range(65)]
+    E = make_ensemble(spec, cases, tune_cache="")
+    assert [g["members"] for g in E.groups()] == [64, 1]
+    for i, c in enumerate(cases):
+        E.set_state(i, dev(c.U))
+    E.step(3)
+    for i in (0, 37, 63, 64):
+        S = make_solo(8, "fp32", cases[i])
+        S.set_state(dev(cases[i].U))
+        S.step(3)
+        assert states_equal(E.get_state(i), S.get_state()), f"member {i}"
+        S.close()
+    E.close()
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    log("[ens] tuning cache")
+    path = tmp_path / "tune.txt"
+    spec = [(16, "fp32", 30), (32, "fp32", 31), (16, "fp32", 32)]
+    cases = [case(n, s) for n, _, s in spec]
+    E = make_ensemble(spec, cases, tune_cache=str(path))
+    for i, c in enumerate(cases):
+        E.set_state(i, dev(c.U))
+    E.step(2)
+    g1 = E.groups()
+    E.close()
+    lines = path.read_text().strip().splitlines()
+    log("  cache", lines)
+    assert len(lines) == 2 and all(l.startswith("mhd-ens-tune ") for l in lines)
+    E2 = make_ensemble(spec, cases, tune_cache=str(path))
+    assert E2.groups() == g1  # read back before any step
+    for i, c in enumerate(cases):
+        E2.set_state(i, dev(c.U))
+    E2.step(2)
+    assert len(path.read_text().strip().splitlines()) == 2  # nothing re-tuned
+    E2.close()
