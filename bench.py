@@ -200,18 +200,14 @@ def pass_table(prof: dict, steps: int):
 def load_traffic(n: int):
     """HBM bytes per launch measured by rocprofv3 counters, if recorded for the
     current kernel sources (profiles/traffic_<n>.json carries a source hash)."""
-    import hashlib
+    from paper_1810_12707_amd.profile_summary import source_sha256
 
     path = os.path.join(ROOT, "profiles", f"traffic_{n}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(ROOT, "paper_1810_12707_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1810_12707_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    if rec.get("source_sha256") != h.hexdigest():
+    if rec.get("source_sha256") != source_sha256():
         return None
     return rec.get("bytes_per_launch")
 

@@ -220,6 +220,31 @@ __device__ __forceinline__ void lane_map(int w, int& b, int& j) {
   }
 }
 
+// Butterfly (sequence b, index j) of first-pass slot i of thread tid, for NB
+// sequences of NBF butterflies spread over NT threads; false if the slot is
+// idle.  MAP 0 and 1 as lane_map on w = tid + i NT.  MAP 2 puts butterflies j
+// and NBF - j of one sequence (j = 0 together with NBF/2) in one thread, as
+// slots i and i + CNT/2: the Hermitian mirror X[N - q] that an element q of
+// one needs is then an element of the other, already in the thread.
+template <int NB, int NBF, int NT, int MAP>
+__device__ __forceinline__ bool first_slot(int tid, int i, int& b, int& j) {
+  constexpr int TOT = NB * NBF;
+  if constexpr (MAP == 2) {
+    constexpr int CNT = (TOT + NT - 1) / NT;
+    static_assert(CNT % 2 == 0 && NBF % 2 == 0, "paired slots need an even slot count");
+    constexpr int H = CNT / 2, HB = NBF / 2;
+    const int u = tid + (i % H) * NT;
+    b = u / HB;
+    const int p = u - b * HB;
+    j = i < H ? p : (p == 0 ? HB : NBF - p);
+    return u < TOT / 2;
+  } else {
+    const int w = tid + i * NT;
+    lane_map<NB, NBF, MAP>(w, b, j);
+    return TOT % NT == 0 || w < TOT;
+  }
+}
+
 // LDS element address of (sequence b, position pos).  PADSH > 0 inserts one
 // padding slot after every 2^PADSH positions, which spreads the strided
 // Stockham writes of row-major sequences over the LDS banks.
@@ -526,10 +551,8 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
   constexpr int NP = PL::np;
 #pragma unroll
   for (int i = 0; i < FP::CNT; ++i) {
-    const int w = tid + i * NT;
     int b, j;
-    lane_map<NB, FP::NBF, MAP>(w, b, j);
-    if ((FP::TOT % NT == 0 || w < FP::TOT) && b < b_act) {
+    if (first_slot<NB, FP::NBF, NT, MAP>(tid, i, b, j) && b < b_act) {
       dft<FP::R, S>(v[i]);
       if constexpr (NP == 1) {
 #pragma unroll

@@ -395,6 +395,7 @@ struct Engine {
   }
 
   int ztiles() const { return (int)(((int64_t)g.nb * g.nhp + k.col_width - 1) / k.col_width); }
+  int rtiles() const { return (int)(((int64_t)g.nb * g.nhp + k.rhs_width - 1) / k.rhs_width); }
   int ytiles() const { return (g.nh + k.col_width - 1) / k.col_width; }
 
   Batch batch() const {
@@ -621,7 +622,7 @@ struct Engine {
     timed(MHD_PASS_RHO, [&] {
       hipLaunchKernelGGL((k_rho_rhs<T>), dim3(sblocks, (unsigned)ms.n), dim3(kThreads), 0, c->stream, q);
     });
-    timed(MHD_PASS_ZRHS, [&] { k.rhs(q, dim3((unsigned)(ztiles() * 7 * ms.n)), c->stream); });
+    timed(MHD_PASS_ZRHS, [&] { k.rhs(q, dim3((unsigned)(rtiles() * 7 * ms.n)), c->stream); });
   }
 
   double step_bytes() const {

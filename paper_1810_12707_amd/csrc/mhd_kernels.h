@@ -27,10 +27,25 @@ template <int N> struct Band {
 template <int N> __device__ __forceinline__ int band_pos(int l) { return l <= Band<N>::K ? l : l + N - Band<N>::NB; }
 template <int N> __device__ __forceinline__ int band_k(int l) { return l <= Band<N>::K ? l : l - Band<N>::NB; }
 
-// Column tile width: 16 columns while the LDS tile stays within 32 KiB, else 8.
+// Tile width of the forward-z RHS pass: 16 columns while its LDS tile stays
+// within 32 KiB, else 8.
 template <typename T, int N> constexpr int col_width() {
   constexpr int bytes = N * 2 * (int)sizeof(T);
   return 32768 / bytes >= 16 ? 16 : 8;
+}
+
+// Threads and tile width of the column passes.  Long FP32 columns (N >= 512)
+// take 512 threads and 16 columns, so that every row segment of a tile is a
+// whole 128-byte line (8 FP32 columns would read half lines, whose other
+// halves another workgroup reads later, often after eviction); the
+// per-thread work, and so the register footprint, equals that of 256
+// threads on 8 columns.  The MFMA variant keeps 256 threads (its registers
+// would not fit two waves per SIMD).
+template <typename T, int N, bool MX> constexpr int col_threads() {
+  return (sizeof(T) == 4 && N >= 512 && !MX) ? 2 * kThreads : kThreads;
+}
+template <typename T, int N, bool MX> constexpr int col_tile() {
+  return col_threads<T, N, MX>() == 2 * kThreads ? 16 : col_width<T, N>();
 }
 
 template <typename T>
@@ -63,9 +78,9 @@ __device__ __forceinline__ cx<T> combine(const OutSpec& sp, const T* const* in, 
   return acc;
 }
 
-template <typename T, int N>
+template <typename T, int N, int NT = kThreads>
 __device__ __forceinline__ void load_twiddles(cx<T>* stw, const T* tw, int tid) {
-  for (int i = tid; i < N; i += kThreads) stw[i] = ld(tw, i);
+  for (int i = tid; i < N; i += NT) stw[i] = ld(tw, i);
 }
 
 // Band index of position q on a length-N axis, or -1 in the dropped gap.
@@ -96,11 +111,12 @@ __device__ __forceinline__ TileField tile_field(int nfields) {
 // (up to MAXT input terms per element; the zero gap of a band input is never
 // loaded); the last pass stores straight to HBM (dropped modes skipped).
 template <typename T, int N, int S, int MAXT, bool MX>
-__global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
+__global__ void __launch_bounds__((col_threads<T, N, MX>())) k_col(const ColArgs<T> a) {
   using PL = PlanOf<N, MX>;
-  constexpr int C = col_width<T, N>();
+  constexpr int C = col_tile<T, N, MX>();
+  constexpr int NT = col_threads<T, N, MX>();
   constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
-  using FP = FirstPass<PL, C, kThreads>;
+  using FP = FirstPass<PL, C, NT>;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
@@ -119,7 +135,7 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
     case PK_YFWD: os_in = (int64_t)N * NHP; ls_in = NHP; os_out = (int64_t)NBB * NHP; ls_out = NHP; break;
     default: os_in = 0; ls_in = NBB * NHP; os_out = 0; ls_out = NBB * NHP; break;
   }
-  load_twiddles<T, N>(stw, a.tw, tid);
+  load_twiddles<T, N, NT>(stw, a.tw, tid);
   auto col_ok = [&](int col) { return col < ncols && (!zpass || col - (col / NHP) * NHP < NH); };
 
   struct Item {
@@ -142,10 +158,10 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
     const int64_t base_in = it.outer * os_in + it.c0;
 #pragma unroll
     for (int i = 0; i < FP::CNT; ++i) {
-      const int w = tid + i * kThreads;
+      const int w = tid + i * NT;
       int c, j;
       lane_map<C, FP::NBF, 0>(w, c, j);
-      const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && col_ok(it.c0 + c);
+      const bool ok = (FP::TOT % NT == 0 || w < FP::TOT) && col_ok(it.c0 + c);
 #pragma unroll
       for (int r = 0; r < FP::R; ++r) {
         const int q = j + r * FP::NBF;
@@ -170,11 +186,11 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
     cx<T> v[FP::CNT][FP::R];
 #pragma unroll
     for (int i = 0; i < FP::CNT; ++i) {
-      const int w = tid + i * kThreads;
+      const int w = tid + i * NT;
       int c, j;
       lane_map<C, FP::NBF, 0>(w, c, j);
       const int col = it.c0 + c;
-      const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && col_ok(col);
+      const bool ok = (FP::TOT % NT == 0 || w < FP::TOT) && col_ok(col);
       int kx, ky = 0;
       if (zpass) {
         ky = band_k<N>(col / NHP);
@@ -225,10 +241,10 @@ __global__ void __launch_bounds__(kThreads) k_col(const ColArgs<T> a) {
       }
       st(out, base_out + l * ls_out + c, val);
     };
-    fft_first_regs<T, PL, C, kThreads, C, 1, S, 0, 0>(tile, v, tid, C, store);
+    fft_first_regs<T, PL, C, NT, C, 1, S, 0, 0>(tile, v, tid, C, store);
     const int next = (int)xcd_item(blockIdx.x, G, k + 1, total);
     if (next >= 0) issue(decode(next));  // in flight during this item's LDS passes
-    fft_rest<T, PL, C, kThreads, C, 1, S, 0, 0>(tile, stw, tid, C, store);
+    fft_rest<T, PL, C, NT, C, 1, S, 0, 0>(tile, stw, tid, C, store);
     item = next;
   }
 }
@@ -437,9 +453,17 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
 
   // Prefetch registers for the next row pair: the two rows' Hermitian
   // half-spectrum entries X0[q], X1[q] behind the first-pass elements in the
-  // lower half (q < N/2, r < R/2).  Elements q >= N-K use X[N-q], which a
-  // mirror lane prefetched, so they are read when used and hit the cache.
+  // lower half (q < N/2, r < R/2).  Elements q >= N-K use X[N-q]: with paired
+  // first-pass slots (FMAP 2) that is a lower-half element of the thread's
+  // partner butterfly, already in these registers; with FMAP 3 it is in a
+  // partner lane's registers; otherwise (FMAP 1) a mirror lane prefetched it
+  // and it is read again when used.
+  // FMAP 3: plain slots, but when NBF divides the wave width the partner
+  // butterfly NBF - j sits in the same wave and the mirror comes by a lane
+  // shuffle of its register.
   constexpr int RH = FP::R / 2;
+  constexpr int FMAP = (FP::CNT % 2 == 0 && FP::NBF % 2 == 0) ? 2 : ((FP::NBF >= 2 && 64 % FP::NBF == 0) ? 3 : 1);
+  constexpr int HC = FP::CNT / 2;
   cx<T> p0[FP::CNT][RH], p1[FP::CNT][RH];
   auto issue = [&](int64_t item) {
     const int mi = (int)(item / rows_per_mem);
@@ -447,10 +471,8 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
     const T* in0 = member_ptr(a.in0, mi, a.bt.mstride);
 #pragma unroll
     for (int i = 0; i < FP::CNT; ++i) {
-      const int w = tid + i * kThreads;
       int b, j;
-      lane_map<NB, FP::NBF, 1>(w, b, j);
-      const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && b < nin;
+      const bool ok = first_slot<NB, FP::NBF, kThreads, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
       const T* src = in0 + 2 * b * a.in_stride;
 #pragma unroll
       for (int r = 0; r < RH; ++r) {
@@ -510,11 +532,11 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
       cx<T> v[FP::CNT][FP::R];
 #pragma unroll
       for (int i = 0; i < FP::CNT; ++i) {
-        const int w = tid + i * kThreads;
         int b, j;
-        lane_map<NB, FP::NBF, 1>(w, b, j);
-        const bool ok = (FP::TOT % kThreads == 0 || w < FP::TOT) && b < nin;
+        const bool ok = first_slot<NB, FP::NBF, kThreads, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
         const T* src = member_ptr(a.in0, mem, a.bt.mstride) + 2 * b * a.in_stride;
+        // FMAP 3: lane of butterfly NBF - j (j = tid mod NBF since NBF divides 64)
+        const int plane = (tid & 63) - j + (FP::NBF - j) % FP::NBF;
 #pragma unroll
         for (int r = 0; r < FP::R; ++r) {
           const int q = j + r * FP::NBF;
@@ -523,9 +545,42 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
             x0 = p0[i][r < RH ? r : 0];
             x1 = p1[i][r < RH ? r : 0];
           }
-          if (ok && q >= N - K) {
-            x0 = ld(src, row0 * NHP + (N - q));
-            x1 = ld(src, (row0 + 1) * NHP + (N - q));
+          cx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+          if constexpr (FMAP == 3) {
+            if (r >= RH) {  // uniform: every lane takes part in the shuffles
+              const int r1 = (FP::R - 1 - r) < RH ? (FP::R - 1 - r) : 0;
+              s0 = mk<T>(__shfl(p0[i][r1].x, plane), __shfl(p0[i][r1].y, plane));
+              s1 = mk<T>(__shfl(p1[i][r1].x, plane), __shfl(p1[i][r1].y, plane));
+            }
+          }
+          if (ok && q >= N - K) {  // only r >= R/2 reach here (j < NBF, K < N/3)
+            if constexpr (FMAP == 3) {
+              // N - q is element R-r-1 of butterfly NBF-j (partner lane), or,
+              // for j = 0, element R-r of the same butterfly
+              const int r0 = (FP::R - r) < RH ? (FP::R - r) : 0;
+              x0 = j == 0 ? p0[i][r0] : s0;
+              x1 = j == 0 ? p1[i][r0] : s1;
+            } else if constexpr (FMAP == 2) {
+              // N - q is element R-r-1 of butterfly NBF-j (the partner slot),
+              // or, for j = 0, element R-r of the same butterfly, or, for
+              // j = NBF/2, element R-r-1 of the same butterfly
+              const int ip = i < HC ? i + HC : i - HC;
+              const int r1 = (FP::R - 1 - r) < RH ? (FP::R - 1 - r) : 0;
+              const int r0 = (FP::R - r) < RH ? (FP::R - r) : 0;
+              if (j == 0) {
+                x0 = p0[i][r0];
+                x1 = p1[i][r0];
+              } else if (j == FP::NBF / 2) {
+                x0 = p0[i][r1];
+                x1 = p1[i][r1];
+              } else {
+                x0 = p0[ip][r1];
+                x1 = p1[ip][r1];
+              }
+            } else {
+              x0 = ld(src, row0 * NHP + (N - q));
+              x1 = ld(src, (row0 + 1) * NHP + (N - q));
+            }
           }
           cx<T> z = mk<T>(0, 0);
           if (ok) {
@@ -536,7 +591,7 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
           v[i][r] = z;
         }
       }
-      fft_first_regs<T, PL, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, v, tid, nin, lds_store);
+      fft_first_regs<T, PL, NB, kThreads, 1, BS, +1, (FMAP == 2 ? 2 : 1), PADSH>(buf, v, tid, nin, lds_store);
       if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
       fft_rest<T, PL, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, lds_store);
     }

@@ -9,7 +9,8 @@ namespace mhd {
 template <typename T>
 struct Kern {
   int n = 0;
-  int col_width = 0;  // columns per workgroup of the column passes
+  int col_width = 0;  // columns per work item of the column passes
+  int rhs_width = 0;  // columns per workgroup of the forward-z RHS pass
   // column passes; maxt = largest number of terms of any output spec (1 or 3)
   void (*col_inv)(int maxt, const ColArgs<T>&, dim3, hipStream_t) = nullptr;
   void (*col_fwd)(const ColArgs<T>&, dim3, hipStream_t) = nullptr;
