@@ -12,27 +12,30 @@ namespace {
 
 template <typename T, int N, bool MX>
 void col_inv(int maxt, const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  constexpr int NT = col_threads<T, N, MX>();
-  if (maxt <= 1) hipLaunchKernelGGL((k_col<T, N, 1, 1, MX>), g, dim3(NT), 0, s, a);
-  else hipLaunchKernelGGL((k_col<T, N, 1, kMaxTerms, MX>), g, dim3(NT), 0, s, a);
+  if (maxt <= 1) hipLaunchKernelGGL((k_col<T, N, 1, 1, MX>), g, dim3(col_threads<T, N, MX, 1, 1>()), 0, s, a);
+  else hipLaunchKernelGGL((k_col<T, N, 1, kMaxTerms, MX>), g, dim3(col_threads<T, N, MX, 1, kMaxTerms>()), 0, s, a);
 }
 template <typename T, int N, bool MX>
 void col_fwd(const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((k_col<T, N, -1, 1, MX>), g, dim3(col_threads<T, N, MX>()), 0, s, a);
+  hipLaunchKernelGGL((k_col<T, N, -1, 1, MX>), g, dim3(col_threads<T, N, MX, -1, 1>()), 0, s, a);
 }
 template <typename T, int N, bool MX>
 int col_occupancy(int dir, int maxt) {
-  constexpr int NT = col_threads<T, N, MX>();
   int blocks = 0;
   hipError_t e;
-  if (dir < 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, -1, 1, MX>, NT, 0);
-  else if (maxt <= 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, 1, MX>, NT, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, kMaxTerms, MX>, NT, 0);
+  if (dir < 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, -1, 1, MX>, col_threads<T, N, MX, -1, 1>(),
+                                                     0);
+  else if (maxt <= 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, 1, MX>, col_threads<T, N, MX, 1, 1>(), 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, kMaxTerms, MX>,
+                                                     col_threads<T, N, MX, 1, kMaxTerms>(), 0);
   return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 template <typename T, int N, bool MX>
 void rhs(const RhsArgs<T>& a, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((k_zfwd_rhs<T, N, MX>), g, dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((k_zfwd_rhs<T, N, MX>), g, dim3(rhs_threads<T, N, MX>()), 0, s, a);
 }
 template <typename T, int N, bool MX>
 void row(int mode, const RowArgs<T>& a, dim3 g, hipStream_t s) {
@@ -70,7 +73,7 @@ Kern<T> make() {
   Kern<T> k;
   k.n = N;
   k.col_width = col_tile<T, N, MX>();
-  k.rhs_width = col_width<T, N>();
+  k.rhs_width = rhs_tile<T, N, MX>();
   k.col_inv = col_inv<T, N, MX>;
   k.col_fwd = col_fwd<T, N, MX>;
   k.rhs = rhs<T, N, MX>;

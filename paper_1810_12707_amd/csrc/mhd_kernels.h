@@ -27,25 +27,46 @@ template <int N> struct Band {
 template <int N> __device__ __forceinline__ int band_pos(int l) { return l <= Band<N>::K ? l : l + N - Band<N>::NB; }
 template <int N> __device__ __forceinline__ int band_k(int l) { return l <= Band<N>::K ? l : l - Band<N>::NB; }
 
-// Tile width of the forward-z RHS pass: 16 columns while its LDS tile stays
-// within 32 KiB, else 8.
+// Default column tile: 16 columns while the LDS tile stays within 32 KiB,
+// else 8.
 template <typename T, int N> constexpr int col_width() {
   constexpr int bytes = N * 2 * (int)sizeof(T);
   return 32768 / bytes >= 16 ? 16 : 8;
 }
 
-// Threads and tile width of the column passes.  Long FP32 columns (N >= 512)
-// take 512 threads and 16 columns, so that every row segment of a tile is a
-// whole 128-byte line (8 FP32 columns would read half lines, whose other
-// halves another workgroup reads later, often after eviction); the
-// per-thread work, and so the register footprint, equals that of 256
-// threads on 8 columns.  The MFMA variant keeps 256 threads (its registers
-// would not fit two waves per SIMD).
-template <typename T, int N, bool MX> constexpr int col_threads() {
-  return (sizeof(T) == 4 && N >= 512 && !MX) ? 2 * kThreads : kThreads;
+// Threads and tile width of the forward-z RHS pass.  It is latency-bound
+// (three dependent memory phases per workgroup: the first flux group, the
+// second, the state and history), so it wants many resident waves: FP32 at
+// N >= 256 runs 512 threads with one first-pass butterfly each (16 columns at
+// N = 256, 8 above), which keeps registers low (five or more waves per SIMD).
+template <typename T, int N, bool MX> constexpr bool rhs_wide() { return sizeof(T) == 4 && N >= 256 && !MX; }
+template <typename T, int N, bool MX> constexpr int rhs_threads() {
+  return rhs_wide<T, N, MX>() ? 2 * kThreads : kThreads;
+}
+template <typename T, int N, bool MX> constexpr int rhs_tile() {
+  return rhs_wide<T, N, MX>() ? (N == 256 ? 16 : 8) : col_width<T, N>();
+}
+// Minimum resident waves per SIMD asked of the compiler (register cap).
+template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs_wide<T, N, MX>() ? 1 : 3; }
+
+// Threads and tile width of the column passes (S = +1 inverse, -1 forward;
+// MAXT input terms per element).  Long FP32 columns take 16-column tiles, so
+// that every row segment is a whole 128-byte line (8 FP32 columns would read
+// half lines, whose other halves another workgroup reads later, often after
+// eviction), and enough threads that each holds one or two first-pass
+// butterflies.  Measured per pass class: one butterfly per thread (fewer
+// registers, more resident waves) pays for the three-term inverse pass at
+// N = 256 and 512 and for the forward passes at N = 512; the one-term
+// inverse passes run best with two.  The MFMA variant keeps 256 threads (its
+// registers would not fit more waves).
+template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
+  if (sizeof(T) != 4 || MX) return kThreads;
+  if (N == 256) return MAXT > 1 ? 2 * kThreads : kThreads;
+  if (N == 512) return (MAXT > 1 || S < 0) ? 4 * kThreads : 2 * kThreads;
+  return N > 512 ? 2 * kThreads : kThreads;
 }
 template <typename T, int N, bool MX> constexpr int col_tile() {
-  return col_threads<T, N, MX>() == 2 * kThreads ? 16 : col_width<T, N>();
+  return (sizeof(T) == 4 && !MX && N >= 256) ? 16 : col_width<T, N>();
 }
 
 template <typename T>
@@ -111,10 +132,10 @@ __device__ __forceinline__ TileField tile_field(int nfields) {
 // (up to MAXT input terms per element; the zero gap of a band input is never
 // loaded); the last pass stores straight to HBM (dropped modes skipped).
 template <typename T, int N, int S, int MAXT, bool MX>
-__global__ void __launch_bounds__((col_threads<T, N, MX>())) k_col(const ColArgs<T> a) {
+__global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(const ColArgs<T> a) {
   using PL = PlanOf<N, MX>;
   constexpr int C = col_tile<T, N, MX>();
-  constexpr int NT = col_threads<T, N, MX>();
+  constexpr int NT = col_threads<T, N, MX, S, MAXT>();
   constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
   using FP = FirstPass<PL, C, NT>;
   __shared__ cx<T> tile[N * C];
@@ -166,6 +187,11 @@ __global__ void __launch_bounds__((col_threads<T, N, MX>())) k_col(const ColArgs
       for (int r = 0; r < FP::R; ++r) {
         const int q = j + r * FP::NBF;
         const int l = S > 0 ? pos_band<N>(q) : q;
+        // the previous item's values are dead: say so, so that the compiler
+        // need not keep them (and wait on loads in flight) when a load below
+        // is predicated off
+#pragma unroll
+        for (int t = 0; t < MAXT; ++t) px[t][i][r] = mk<T>(0, 0);
         if (ok && l >= 0) {
           const int64_t idx = base_in + l * ls_in + c;
 #pragma unroll
@@ -253,12 +279,13 @@ __global__ void __launch_bounds__((col_threads<T, N, MX>())) k_col(const ColArgs
 // Flat grid over (member, column tile of (ky, kx), output field f = 1..7),
 // field fastest.
 template <typename T, int N, bool MX>
-__global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
+__global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N, MX>())) k_zfwd_rhs(const RhsArgs<T> a) {
   using PL = PlanOf<N, MX>;
-  constexpr int C = col_width<T, N>();
+  constexpr int C = rhs_tile<T, N, MX>();
+  constexpr int NT = rhs_threads<T, N, MX>();
   constexpr int NH = Band<N>::NH, NHP = Band<N>::NHP, NBB = Band<N>::NB;
   constexpr int NCOLS = NBB * NHP;  // flattened (ky, kx) over the padded pitch
-  using LP = LastPass<PL, C, kThreads>;
+  using LP = LastPass<PL, C, NT>;
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
@@ -293,7 +320,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
     }
   };
 
-  load_twiddles<T, N>(stw, a.tw, tid);
+  load_twiddles<T, N, NT>(stw, a.tw, tid);
   cx<T> acc[LP::CNT][LP::R];
 #pragma unroll
   for (int i = 0; i < LP::CNT; ++i)
@@ -344,7 +371,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
         acc[i][r].y += kz * v.x;
       }
     };
-    fft_reg<T, PL, C, kThreads, C, 1, -1>(tile, stw, tid, C, load, store);
+    fft_reg<T, PL, C, NT, C, 1, -1>(tile, stw, tid, C, load, store);
   }
   // epilogue over this thread's last-pass positions: resistive term, update
   const T eta = T(a.eta[mem]);
@@ -353,7 +380,7 @@ __global__ void __launch_bounds__(kThreads, 3) k_zfwd_rhs(const RhsArgs<T> a) {
 #pragma unroll
     for (int r = 0; r < LP::R; ++r) {
       int c, q;
-      if (!last_slot<PL, C, kThreads, 0>(tid, i, r, c, q)) continue;
+      if (!last_slot<PL, C, NT, 0>(tid, i, r, c, q)) continue;
       const int col = c0 + c;
       const int kx = col - (col / NHP) * NHP;
       if (col >= NCOLS || kx >= NH) continue;
@@ -477,6 +504,8 @@ __global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
 #pragma unroll
       for (int r = 0; r < RH; ++r) {
         const int q = j + r * FP::NBF;
+        p0[i][r] = mk<T>(0, 0);  // the previous pair's values are dead
+        p1[i][r] = mk<T>(0, 0);
         if (ok && q <= K) {
           p0[i][r] = ld(src, row0 * NHP + q);
           p1[i][r] = ld(src, (row0 + 1) * NHP + q);

@@ -181,6 +181,36 @@ def cmd_traffic(a) -> int:
     return 0
 
 
+def cmd_pmc(a) -> int:
+    """Mean of every counter in the given runs per launch class."""
+    table = {}
+    counters = []
+    for path in a.csv:
+        names = set()
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                names.add(r["Counter_Name"])
+        for c in sorted(names):
+            counters.append(c)
+            table[c] = per_class_kib(path, c, a.n)
+    lines = [f"# Hardware counters per launch: {a.title}", "", "Commands (<repo> = the repository root; one pass "
+             "per counter group):", "", "```", a.command, "```", "",
+             "Mean value per launch of each class (dispatches matched to the step's launch sequence).", "",
+             "| class | " + " | ".join(counters) + " |", "|---|" + "---:|" * len(counters)]
+    for c, _ in STEP_SEQUENCE:
+        vals = []
+        for k in counters:
+            v = table[k].get(c)
+            vals.append(f"{v[0]:.4g}" if v else "-")
+        lines.append(f"| {c} | " + " | ".join(vals) + " |")
+    if a.note:
+        lines += ["", a.note]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {a.out}")
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="what", required=True)
@@ -203,8 +233,15 @@ def main(argv=None) -> int:
     t.add_argument("--out", required=True)
     t.add_argument("--note", default="")
     t.add_argument("--bench-out", default="", help="stdout of one profiled bench.py run (algorithmic bytes)")
+    c = sub.add_parser("pmc")
+    c.add_argument("--n", type=int, required=True)
+    c.add_argument("--csv", nargs="+", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--out", required=True)
+    c.add_argument("--note", default="")
     a = ap.parse_args(argv)
-    return cmd_stats(a) if a.what == "stats" else cmd_traffic(a)
+    return {"stats": cmd_stats, "traffic": cmd_traffic, "pmc": cmd_pmc}[a.what](a)
 
 
 if __name__ == "__main__":
