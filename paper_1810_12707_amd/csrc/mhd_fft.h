@@ -154,8 +154,13 @@ template <int NN, bool MXX, int... Rs> struct PlanT {
   static constexpr int np = sizeof...(Rs);
 };
 
-// FP32 / FP64 plans (VALU only) and mixed plans (radix-16 stages after the
-// first pass, which reads from global memory and stays on the VALU).
+// FP32 / FP64 plans (VALU only) and mixed plans.  A mixed plan ends in a
+// radix-16 stage: the last Stockham pass writes each butterfly onto its own
+// inputs, so the MFMA products run group by group with no registers held
+// across a barrier.  Radix-16 stages before it would (a middle pass must
+// hold every group's products until all groups have read), and a radix-16
+// first pass, which reads from global memory, stays on the VALU; measured
+// fastest: small radices first, one radix-16 MFMA stage last.
 template <int N, bool MX> struct PlanSel;
 #define MHD_PLAN(NN, ...) template <> struct PlanSel<NN, false> { using type = PlanT<NN, false, __VA_ARGS__>; };
 #define MHD_PLAN_MX(NN, ...) template <> struct PlanSel<NN, true> { using type = PlanT<NN, true, __VA_ARGS__>; };
@@ -184,11 +189,11 @@ MHD_PLAN_MX(64, 4, 16)
 MHD_PLAN_MX(96, 2, 3, 16)
 MHD_PLAN_MX(128, 8, 16)
 MHD_PLAN_MX(192, 4, 3, 16)
-MHD_PLAN_MX(256, 16, 16)
+MHD_PLAN_MX(256, 4, 4, 16)
 MHD_PLAN_MX(384, 3, 8, 16)
-MHD_PLAN_MX(512, 2, 16, 16)
-MHD_PLAN_MX(768, 3, 16, 16)
-MHD_PLAN_MX(1024, 4, 16, 16)
+MHD_PLAN_MX(512, 8, 4, 16)
+MHD_PLAN_MX(768, 16, 3, 16)
+MHD_PLAN_MX(1024, 8, 8, 16)
 #undef MHD_PLAN
 #undef MHD_PLAN_MX
 template <int N, bool MX = false> using PlanOf = typename PlanSel<N, MX>::type;
@@ -405,7 +410,7 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
 // multiplied and handed to store(s, t, b, pos, value) (s = group slot of this
 // wave, t = 0..3 the lane's four outputs) before the next group is read.
 // store() may write the LDS positions in place.
-template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH, class Store>
+template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH, class Store, bool SLOTS = false>
 __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const float2* tw, int tid, int b_act,
                                                    Store&& store) {
   constexpr int N = PL::N;
@@ -421,8 +426,7 @@ __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const floa
   const int n = lane & 15, g = lane >> 4;
   bf16x8 a0h, a0l, a1h, a1l;
   dft16_operands<S>(lane, a0h, a0l, a1h, a1l);
-#pragma unroll
-  for (int s = 0; s < GPW; ++s) {
+  auto group = [&](int s) {
     const int grp = wv + s * NW;
     const int w = grp * 16 + n;
     int b, j;
@@ -453,6 +457,16 @@ __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const floa
 #pragma unroll
       for (int t = 0; t < 4; ++t) store(s, t, b, j + (4 * g + t) * NS, make_float2(c0[t], c1[t]));
     }
+  };
+  // The groups run one after another.  The loop is unrolled only when the
+  // store keeps its results in registers indexed by the group slot; rolled,
+  // the compiler cannot hoist every group's loads and hold them all.
+  if constexpr (SLOTS) {
+#pragma unroll
+    for (int s = 0; s < GPW; ++s) group(s);
+  } else {
+#pragma unroll 1
+    for (int s = 0; s < GPW; ++s) group(s);
   }
 }
 
@@ -570,7 +584,8 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
 // store(i, r, b, pos, value) with pos = j + r N/R for the thread's i-th
 // butterfly j.  On the VALU the last pass computes straight into registers;
 // an MFMA last pass writes LDS and the same (i, r, pos) are then read back.
-template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, bool SLOTS = false,
+          class Store>
 __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Store&& store) {
   constexpr int NP = PL::np;
   if constexpr (NP > 1) {
@@ -582,14 +597,14 @@ __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, i
     constexpr int TOT = NB * NBF;
     constexpr int CNT = (TOT + NT - 1) / NT;
     if constexpr (PL::MX && R == 16) {
-      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH>(
-          reinterpret_cast<const float2*>(buf), reinterpret_cast<const float2*>(tw), tid, b_act,
-          [&](int i, int r, int b, int pos, float2 v) {
-            cx<T> vv;
-            vv.x = v.x;
-            vv.y = v.y;
-            store(i, r, b, pos, vv);
-          });
+      auto st2 = [&](int i, int r, int b, int pos, float2 v) {
+        cx<T> vv;
+        vv.x = v.x;
+        vv.y = v.y;
+        store(i, r, b, pos, vv);
+      };
+      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH, decltype(st2)&, SLOTS>(
+          reinterpret_cast<const float2*>(buf), reinterpret_cast<const float2*>(tw), tid, b_act, st2);
     } else {
 #pragma unroll
       for (int i = 0; i < CNT; ++i) {
@@ -621,7 +636,7 @@ __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, i
 // so their memory requests are in flight together.  For one-pass plans the
 // inputs go straight from load() through the DFT to store().  The LDS buffer
 // may be reused after this returns only past a __syncthreads().
-template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, class Load,
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, bool SLOTS = false, class Load,
           class Store>
 __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Load&& load,
                                         Store&& store) {
@@ -638,7 +653,7 @@ __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, in
     for (int r = 0; r < FP::R; ++r) v[i][r] = ok ? load(b, j + r * FP::NBF) : mk<T>(0, 0);
   }
   fft_first_regs<T, PL, NB, NT, ES, BS, S, MAP, PADSH>(buf, v, tid, b_act, store);
-  fft_rest<T, PL, NB, NT, ES, BS, S, MAP, PADSH>(buf, tw, tid, b_act, store);
+  fft_rest<T, PL, NB, NT, ES, BS, S, MAP, PADSH, SLOTS>(buf, tw, tid, b_act, store);
 }
 
 // Item order of a persistent grid of G workgroups over `total` items: the

@@ -39,7 +39,7 @@ template <typename T, int N> constexpr int col_width() {
 // second, the state and history), so it wants many resident waves: FP32 at
 // N >= 256 runs 512 threads with one first-pass butterfly each (16 columns at
 // N = 256, 8 above), which keeps registers low (five or more waves per SIMD).
-template <typename T, int N, bool MX> constexpr bool rhs_wide() { return sizeof(T) == 4 && N >= 256 && !MX; }
+template <typename T, int N, bool MX> constexpr bool rhs_wide() { return sizeof(T) == 4 && N >= 256; }
 template <typename T, int N, bool MX> constexpr int rhs_threads() {
   return rhs_wide<T, N, MX>() ? 2 * kThreads : kThreads;
 }
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
         acc[i][r].y += kz * v.x;
       }
     };
-    fft_reg<T, PL, C, NT, C, 1, -1>(tile, stw, tid, C, load, store);
+    fft_reg<T, PL, C, NT, C, 1, -1, 0, 0, true>(tile, stw, tid, C, load, store);
   }
   // epilogue over this thread's last-pass positions: resistive term, update
   const T eta = T(a.eta[mem]);

@@ -48,12 +48,14 @@ def sampled_dft(f, ks):
     return np.array(out)
 
 
-@pytest.mark.parametrize("n", [256, 512])
-def test_fft_sampled_coefficients(n):
-    log(f"[fullsize fft] n={n}")
+@pytest.mark.parametrize("n,prec", [(256, "fp32"), (512, "fp32"), (512, "mixed")])
+def test_fft_sampled_coefficients(n, prec):
+    """Mixed: the BF16 split keeps ~16 bits per product, so its bar is the
+    mixed transform bar (2e-4 relative L2) with the max-over-samples margin."""
+    log(f"[fullsize fft] n={n} prec={prec}")
     rng = np.random.default_rng(7 + n)
     f = rng.standard_normal((n, n, n), dtype=np.float32)
-    S = solver(n, "fp32")
+    S = solver(n, prec)
     spec = S.fft_forward(torch.from_numpy(f).to("cuda:0"))
     torch.cuda.synchronize()
     K, nb, _ = band(n)
@@ -67,7 +69,7 @@ def test_fft_sampled_coefficients(n):
     scale = n ** 1.5  # rms of a coefficient of unit white noise
     err = np.max(np.abs(got - ref)) / scale
     log(f"  max |error| / n^1.5 = {err:.3e}")
-    assert err <= 1e-5
+    assert err <= (1e-5 if prec == "fp32" else 2e-3)
     S.close()
 
 
@@ -132,7 +134,8 @@ def low_mode_coefficients(R, kmax):
     return out
 
 
-@pytest.mark.parametrize("n,prec", [(256, "fp32"), (512, "fp32"), (256, "fp64"), (512, "fp64")])
+@pytest.mark.parametrize("n,prec", [(256, "fp32"), (512, "fp32"), (256, "fp64"), (512, "fp64"), (256, "mixed"),
+                                    (512, "mixed")])
 def test_rhs_exact_lowmode_state(n, prec):
     """FP64: pointwise at sampled grid points.  FP32: the rounding of P ~ 2 to
     FP32 is white noise over every mode up to K, and the divergence multiplies
@@ -151,7 +154,7 @@ def test_rhs_exact_lowmode_state(n, prec):
     keep = (np.abs(kx) <= 6) & (np.abs(ky) <= 6) & (np.abs(kz) <= 6)
     # the exact RHS lives on |k_i| <= 6: nothing else may be present
     assert np.max(np.abs(F[:, ~keep])) <= 1e-12 * np.max(np.abs(F))
-    dt_ = torch.float32 if prec == "fp32" else torch.float64
+    dt_ = torch.float64 if prec == "fp64" else torch.float32
     Un = torch.empty((8, n, n, n), dtype=dt_, device="cuda:0")
     for f in range(8):
         Un[f] = torch.from_numpy(upsample_field(U0[f], n)).to("cuda:0", dtype=dt_)
@@ -176,6 +179,10 @@ def test_rhs_exact_lowmode_state(n, prec):
         got = low_mode_coefficients(out, 6).cpu().numpy()
         K = (n - 1) // 3
         noise = 1.2e-7 * 3.0 * np.sqrt(3.0) * K        # eps * |P|-scale * max |k|, absolute
+        low_tol = 1e-5
+        if prec == "mixed":  # BF16 split: ~2^8 x the FP32 rounding per product, the mixed bound 1e-3
+            noise *= 256.0
+            low_tol = 1e-3
         for f in range(8):
             e = np.linalg.norm(got[f] - exact[f]) / np.linalg.norm(exact[f])
             tot = float(torch.linalg.vector_norm(out[f].double())) ** 2 / n ** 3      # <R^2>
@@ -183,7 +190,7 @@ def test_rhs_exact_lowmode_state(n, prec):
             rest = np.sqrt(max(tot - low, 0.0))
             log(f"  field {I.FIELD_NAMES[f]}: low modes rel {e:.3e}; rms outside {rest:.3e} "
                 f"(bound {noise:.1e}, rms R {np.sqrt(low):.3e})")
-            assert e <= 1e-5, (f, e)
+            assert e <= low_tol, (f, e)
             assert rest <= noise, (f, rest, noise)
     S.close()
 
