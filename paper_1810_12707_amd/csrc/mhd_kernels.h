@@ -57,16 +57,16 @@ template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs
 // butterflies.  Measured per pass class: one butterfly per thread (fewer
 // registers, more resident waves) pays for the three-term inverse pass at
 // N = 256 and 512 and for the forward passes at N = 512; the one-term
-// inverse passes run best with two.  The MFMA variant keeps 256 threads (its
-// registers would not fit more waves).
+// inverse passes run best with two.  The MFMA variant follows the same rule
+// from N = 512 up and keeps 256 threads below (measured).
 template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
-  if (sizeof(T) != 4 || MX) return kThreads;
+  if (sizeof(T) != 4 || (MX && N < 512)) return kThreads;
   if (N == 256) return MAXT > 1 ? 2 * kThreads : kThreads;
   if (N == 512) return (MAXT > 1 || S < 0) ? 4 * kThreads : 2 * kThreads;
   return N > 512 ? 2 * kThreads : kThreads;
 }
 template <typename T, int N, bool MX> constexpr int col_tile() {
-  return (sizeof(T) == 4 && !MX && N >= 256) ? 16 : col_width<T, N>();
+  return (sizeof(T) == 4 && N >= 256) ? 16 : col_width<T, N>();
 }
 
 template <typename T>
@@ -457,8 +457,11 @@ __device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status) {
   }
 }
 
+// The MFMA variant is held to two waves per SIMD: left free, the flux pass
+// took more than 256 registers at N = 512 and ran one wave per SIMD, 1.3x
+// slower than capped with a small spill.
 template <typename T, int N, int MODE, bool MX>
-__global__ void __launch_bounds__(kThreads) k_row(const RowArgs<T> a) {
+__global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T> a) {
   using PL = PlanOf<N, MX>;
   constexpr int K = Band<N>::K, NHP = Band<N>::NHP;
   constexpr int NH = Band<N>::NH;
