@@ -63,6 +63,8 @@ def make_case(name: str):
         return I.random_turbulence(int(name[4:]), name=name)
     if name.startswith("abc"):
         return I.abc_dynamo(int(name[3:]), 1e-3, 1e-3, None, 200, name=name)
+    if name.startswith("ot"):
+        return I.orszag_tang(int(name[2:]), name=name)
     raise ValueError(name)
 
 
@@ -72,6 +74,10 @@ def describe(case) -> str:
         return (f"{n}^3 random-phase MHD turbulence, FP32: solenoidal u E(k)~k^-2 shells 1-8 Mach 0.3, "
                 f"B rms 0.1 shells 1-4, rho=1+-1%, gamma=5/3, nu=eta={case.nu:g}, dt={case.dt:.3e} (CFL 0.1), "
                 "AB2, 2/3 dealiasing")
+    if case.name.startswith("ot"):
+        return (f"{n}^3 Orszag-Tang-type start, FP32: u=(-sin y, sin x, 0), B=(-sin y, sin 2x, 0) plus solenoidal "
+                f"shells 1-4 of rms 1e-2 in u and B, rho=25/9, P=5/3, gamma=5/3, nu=eta={case.nu:g}, "
+                f"dt={case.dt:.3e} (CFL 0.1), AB2, 2/3 dealiasing")
     return (f"{n}^3 ABC-flow dynamo start, FP32: rho=1, ABC u (A=B=C=1, k=1), B rms 1e-3 shells 1-4, Mach 0.1, "
             f"gamma=5/3, nu=eta={case.nu:g}, dt={case.dt:.3e} (CFL 0.1), AB2, 2/3 dealiasing")
 
@@ -309,7 +315,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="turb256", help="turb256 (default), abc512, turbN, abcN")
+    ap.add_argument("--config", default="turb256", help="turb256 (default), abc512, turbN, abcN, otN")
     ap.add_argument("--secondary", default="abc512", help="second workload reported alongside ('' = none)")
     ap.add_argument("--secondary-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -40,11 +40,11 @@ void rhs(const RhsArgs<T>& a, dim3 g, hipStream_t s) {
 template <typename T, int N, bool MX>
 void row(int mode, const RowArgs<T>& a, dim3 g, hipStream_t s) {
   switch (mode) {
-    case RM_XA: hipLaunchKernelGGL((k_row<T, N, RM_XA, MX>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XB: hipLaunchKernelGGL((k_row<T, N, RM_XB, MX>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XFWD_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XFWD_REAL, MX>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XINV_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XINV_REAL, MX>), g, dim3(kThreads), 0, s, a); break;
-    case RM_XDIAG: hipLaunchKernelGGL((k_row<T, N, RM_XDIAG, MX>), g, dim3(kThreads), 0, s, a); break;
+    case RM_XA: hipLaunchKernelGGL((k_row<T, N, RM_XA, MX>), g, dim3(row_threads<T, N, RM_XA, MX>()), 0, s, a); break;
+    case RM_XB: hipLaunchKernelGGL((k_row<T, N, RM_XB, MX>), g, dim3(row_threads<T, N, RM_XB, MX>()), 0, s, a); break;
+    case RM_XFWD_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XFWD_REAL, MX>), g, dim3(row_threads<T, N, RM_XFWD_REAL, MX>()), 0, s, a); break;
+    case RM_XINV_REAL: hipLaunchKernelGGL((k_row<T, N, RM_XINV_REAL, MX>), g, dim3(row_threads<T, N, RM_XINV_REAL, MX>()), 0, s, a); break;
+    case RM_XDIAG: hipLaunchKernelGGL((k_row<T, N, RM_XDIAG, MX>), g, dim3(row_threads<T, N, RM_XDIAG, MX>()), 0, s, a); break;
     default: break;
   }
 }
@@ -54,15 +54,20 @@ int row_occupancy(int mode) {
   int blocks = 0;
   hipError_t e = hipSuccess;
   switch (mode) {
-    case RM_XA: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XA, MX>, kThreads, 0); break;
-    case RM_XB: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XB, MX>, kThreads, 0); break;
+    case RM_XA: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XA, MX>,
+                                                     row_threads<T, N, RM_XA, MX>(), 0); break;
+    case RM_XB: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XB, MX>,
+                                                     row_threads<T, N, RM_XB, MX>(), 0); break;
     case RM_XFWD_REAL:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XFWD_REAL, MX>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XFWD_REAL, MX>,
+                                                     row_threads<T, N, RM_XFWD_REAL, MX>(), 0);
       break;
     case RM_XINV_REAL:
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XINV_REAL, MX>, kThreads, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XINV_REAL, MX>,
+                                                     row_threads<T, N, RM_XINV_REAL, MX>(), 0);
       break;
-    case RM_XDIAG: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XDIAG, MX>, kThreads, 0); break;
+    case RM_XDIAG: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_row<T, N, RM_XDIAG, MX>,
+                                                     row_threads<T, N, RM_XDIAG, MX>(), 0); break;
     default: break;
   }
   return (e == hipSuccess && blocks > 0) ? blocks : 1;

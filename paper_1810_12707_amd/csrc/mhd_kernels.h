@@ -57,8 +57,10 @@ template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs
 // butterflies.  Measured per pass class: one butterfly per thread (fewer
 // registers, more resident waves) pays for the three-term inverse pass at
 // N = 256 and 512 and for the forward passes at N = 512; the one-term
-// inverse passes run best with two.  The MFMA variant follows the same rule
-// from N = 512 up and keeps 256 threads below (measured).
+// inverse passes run best with two.  Above 512 (LDS-limited to one
+// workgroup per CU) 512 threads on 8 columns avoid register spills.  The
+// MFMA variant follows the same rule from N = 512 up and keeps 256 threads
+// below (measured).
 template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
   if (sizeof(T) != 4 || (MX && N < 512)) return kThreads;
   if (N == 256) return MAXT > 1 ? 2 * kThreads : kThreads;
@@ -66,7 +68,7 @@ template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads
   return N > 512 ? 2 * kThreads : kThreads;
 }
 template <typename T, int N, bool MX> constexpr int col_tile() {
-  return (sizeof(T) == 4 && N >= 256) ? 16 : col_width<T, N>();
+  return (sizeof(T) == 4 && N >= 256 && N <= 512) ? 16 : col_width<T, N>();
 }
 
 template <typename T>
@@ -416,11 +418,12 @@ __device__ __forceinline__ bool finite_(T v) { return isfinite(v); }
 
 // Fixed-order tree reduction over the block (sum, or NaN-propagating max);
 // the result is valid in thread 0.  Deterministic for a given launch shape.
+template <int NT = kThreads>
 __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s, int tid) {
   __syncthreads();
   s[tid] = v;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (tid < w) {
       const double o = s[tid + w];
       if (is_max) {
@@ -443,12 +446,12 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s,
 // words: an unsigned max over the bit patterns of non-negative floats orders
 // them like the floats (NaN sorts above every finite value), and integer adds
 // commute, so the result does not depend on block order.  Block-uniform call.
-template <typename T>
+template <int NT, typename T>
 __device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status) {
-  __shared__ double s_red[kThreads];
+  __shared__ double s_red[NT];
   const int tid = threadIdx.x;
-  const double cfl_b = block_reduce(double(cfl), true, s_red, tid);
-  const double bad_b = block_reduce(double(bad), false, s_red, tid);
+  const double cfl_b = block_reduce<NT>(double(cfl), true, s_red, tid);
+  const double bad_b = block_reduce<NT>(double(bad), false, s_red, tid);
   if (tid == 0) {
     const float cf = float(cfl_b);
     const unsigned bits = (cf != cf) ? 0x7fc00000u : (cf > 0.f ? __float_as_uint(cf) : 0u);
@@ -457,19 +460,27 @@ __device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status) {
   }
 }
 
+// Threads of a row pass: FP32 rows of N >= 1024 take 512, which keeps the
+// per-thread first-pass work (and registers) of N = 512 on 256 threads.
+template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
+  return (sizeof(T) == 4 && N >= 1024) ? 2 * kThreads : kThreads;
+}
+
 // The MFMA variant is held to two waves per SIMD: left free, the flux pass
 // took more than 256 registers at N = 512 and ran one wave per SIMD, 1.3x
 // slower than capped with a small spill.
 template <typename T, int N, int MODE, bool MX>
-__global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T> a) {
+__global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()),
+                                  (MX ? 2 * kThreads / row_threads<T, N, MODE, MX>() : 1)) k_row(const RowArgs<T> a) {
   using PL = PlanOf<N, MX>;
+  constexpr int NT = row_threads<T, N, MODE, MX>();
   constexpr int K = Band<N>::K, NHP = Band<N>::NHP;
   constexpr int NH = Band<N>::NH;
   constexpr int NB = RowShape<MODE>::NB;
   constexpr int PADSH = 3;                    // one LDS padding slot per 8 elements
   constexpr int BS = N + (N >> PADSH) + 1;   // padded row pitch in LDS
   constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
-  using FP = FirstPass<PL, NB, kThreads>;
+  using FP = FirstPass<PL, NB, NT>;
   auto at = [](int b, int pos) { return lds_at<1, BS, PADSH>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
@@ -478,7 +489,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
   const int64_t nitems = rows_per_mem * a.bt.nmem;
   const int nin = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NIN;
   const int nout = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NOUT;
-  load_twiddles<T, N>(stw, a.tw, tid);
+  load_twiddles<T, N, NT>(stw, a.tw, tid);
   auto lds_store = [&](int, int, int fld, int q, cx<T> v) { buf[at(fld, q)] = v; };
 
   // Prefetch registers for the next row pair: the two rows' Hermitian
@@ -502,7 +513,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
 #pragma unroll
     for (int i = 0; i < FP::CNT; ++i) {
       int b, j;
-      const bool ok = first_slot<NB, FP::NBF, kThreads, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
+      const bool ok = first_slot<NB, FP::NBF, NT, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
       const T* src = in0 + 2 * b * a.in_stride;
 #pragma unroll
       for (int r = 0; r < RH; ++r) {
@@ -534,7 +545,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
     if constexpr (MODE == RM_XB) {
       if (mem != cur_m) {  // uniform across the workgroup
         if (cur_m >= 0) {
-          flush_status(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
+          flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
           cfl = T(0);
           bad = 0;
         }
@@ -544,7 +555,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
     __syncthreads();  // the previous row pair is done with the LDS
     if constexpr (!SPEC_IN) {
       // real rows -> packed complex row0 + i row1
-      for (int e = tid; e < nin * N; e += kThreads) {
+      for (int e = tid; e < nin * N; e += NT) {
         const int fld = e / N, x = e - (e / N) * N;
         const int64_t base = fld * a.g.n3 + row0 * N + x;
         T r0, r1;
@@ -565,7 +576,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
 #pragma unroll
       for (int i = 0; i < FP::CNT; ++i) {
         int b, j;
-        const bool ok = first_slot<NB, FP::NBF, kThreads, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
+        const bool ok = first_slot<NB, FP::NBF, NT, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
         const T* src = member_ptr(a.in0, mem, a.bt.mstride) + 2 * b * a.in_stride;
         // FMAP 3: lane of butterfly NBF - j (j = tid mod NBF since NBF divides 64)
         const int plane = (tid & 63) - j + (FP::NBF - j) % FP::NBF;
@@ -623,14 +634,14 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
           v[i][r] = z;
         }
       }
-      fft_first_regs<T, PL, NB, kThreads, 1, BS, +1, (FMAP == 2 ? 2 : 1), PADSH>(buf, v, tid, nin, lds_store);
+      fft_first_regs<T, PL, NB, NT, 1, BS, +1, (FMAP == 2 ? 2 : 1), PADSH>(buf, v, tid, nin, lds_store);
       if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
-      fft_rest<T, PL, NB, kThreads, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, lds_store);
+      fft_rest<T, PL, NB, NT, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, lds_store);
     }
     __syncthreads();
 
     if constexpr (MODE == RM_XINV_REAL) {
-      for (int e = tid; e < nout * N; e += kThreads) {
+      for (int e = tid; e < nout * N; e += NT) {
         const int fld = e / N, x = e - (e / N) * N;
         const cx<T> z = buf[at(fld, x)];
         const int64_t base = fld * a.g.n3 + row0 * N + x;
@@ -647,7 +658,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
 
     if constexpr (MODE == RM_XA) {
       // u = m / rho, both rows at once
-      for (int x = tid; x < N; x += kThreads) {
+      for (int x = tid; x < N; x += NT) {
         const cx<T> rho = buf[at(0, x)];
         const T i0 = T(1) / rho.x, i1 = T(1) / rho.y;
 #pragma unroll
@@ -665,7 +676,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
       // 4 Pi_xz, 5 Pi_yz, 6-8 F^E, 9-11 e = u x B.
       const T gm1 = T(a.gamma[mem] - 1.0), gam = T(a.gamma[mem]), two_nu = T(2.0 * a.nu[mem]),
               eta = T(a.eta[mem]);
-      for (int x = tid; x < N; x += kThreads) {
+      for (int x = tid; x < N; x += NT) {
         cx<T> v[16];
 #pragma unroll
         for (int f = 0; f < 16; ++f) v[f] = buf[at(f, x)];
@@ -723,7 +734,7 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
     if constexpr (MODE == RM_XDIAG) {
       // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8-10 J, 11 div B.
       const double gm1 = a.gamma[mem] - 1.0, gam = a.gamma[mem];
-      for (int x = tid; x < N; x += kThreads) {
+      for (int x = tid; x < N; x += NT) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           auto g = [&](int f) -> double { const cx<T> v = buf[at(f, x)]; return double(h == 0 ? v.x : v.y); };
@@ -759,11 +770,11 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
 
     if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
       __syncthreads();
-      lds_fft<T, PL, NB, kThreads, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
+      lds_fft<T, PL, NB, NT, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
       // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
       T* out0 = member_ptr(a.out0, mem, a.bt.mstride);
       const int64_t ost = a.out_stride;
-      for (int e = tid; e < nout * NH; e += kThreads) {
+      for (int e = tid; e < nout * NH; e += NT) {
         const int fld = e / NH, k = e - (e / NH) * NH;
         const cx<T> zk = buf[at(fld, k)];
         const cx<T> zm = buf[at(fld, k == 0 ? 0 : N - k)];
@@ -777,12 +788,12 @@ __global__ void __launch_bounds__(kThreads, (MX ? 2 : 1)) k_row(const RowArgs<T>
   }
 
   if constexpr (MODE == RM_XB) {
-    if (cur_m >= 0) flush_status(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
+    if (cur_m >= 0) flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
   }
   if constexpr (MODE == RM_XDIAG) {
-    __shared__ double s_red[kThreads];
+    __shared__ double s_red[NT];
     for (int i = 0; i < kDiagQ; ++i) {
-      const double r = block_reduce(q[i], i == DQ_DIVB_MAX || i == DQ_CFL_MAX, s_red, tid);
+      const double r = block_reduce<NT>(q[i], i == DQ_DIVB_MAX || i == DQ_CFL_MAX, s_red, tid);
       if (tid == 0) a.partials[(int64_t)blockIdx.x * kDiagQ + i] = r;
     }
   }

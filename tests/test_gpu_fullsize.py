@@ -48,7 +48,7 @@ def sampled_dft(f, ks):
     return np.array(out)
 
 
-@pytest.mark.parametrize("n,prec", [(256, "fp32"), (512, "fp32"), (512, "mixed")])
+@pytest.mark.parametrize("n,prec", [(256, "fp32"), (512, "fp32"), (512, "mixed"), (1024, "fp32")])
 def test_fft_sampled_coefficients(n, prec):
     """Mixed: the BF16 split keeps ~16 bits per product, so its bar is the
     mixed transform bar (2e-4 relative L2) with the max-over-samples margin."""
@@ -109,6 +109,25 @@ def upsample_field(a, n, kmax=2):
     return sf.irfftn(G, s=(n, n, n), workers=8) * n ** 3
 
 
+def upsample_field_gpu(a, n, kmax=2):
+    """As upsample_field, evaluated on the GPU in FP64 by separable sums over
+    the few modes (x, then y, then z): returns an n^3 float64 CUDA tensor."""
+    n0 = a.shape[-1]
+    F = np.fft.fftn(a) / n0 ** 3                     # [kz][ky][kx]
+    ks = np.r_[-kmax:kmax + 1]
+    C = torch.from_numpy(np.ascontiguousarray(F[np.ix_(ks % n0, ks % n0, ks % n0)])).to("cuda:0")
+    x = torch.arange(n, device="cuda:0", dtype=torch.float64) * (2 * np.pi / n)
+    kk = torch.from_numpy(ks.astype(np.float64)).to("cuda:0")
+    E = torch.exp(1j * torch.outer(kk, x))           # [k][x] complex128
+    m = len(ks)
+    A = (C.reshape(m * m, m) @ E).reshape(m, m, n)  # [kz][ky][x]
+    A = (A.permute(0, 2, 1).reshape(m * n, m) @ E).reshape(m, n, n).permute(0, 2, 1)  # [kz][y][x]
+    A = A.reshape(m, n * n)
+    out = (E.real.transpose(0, 1).contiguous() @ A.real.contiguous()
+           - E.imag.transpose(0, 1).contiguous() @ A.imag.contiguous())                  # [z][y x]
+    return out.reshape(n, n, n)
+
+
 def eval_points(coef, kvec, pts, n):
     """sum_k coef[k] exp(i k.x) at grid points pts (z, y, x indices) of the n grid."""
     x = 2 * np.pi * pts[:, ::-1] / n            # (x, y, z)
@@ -135,7 +154,7 @@ def low_mode_coefficients(R, kmax):
 
 
 @pytest.mark.parametrize("n,prec", [(256, "fp32"), (512, "fp32"), (256, "fp64"), (512, "fp64"), (256, "mixed"),
-                                    (512, "mixed")])
+                                    (512, "mixed"), (1024, "fp32"), (1024, "mixed")])
 def test_rhs_exact_lowmode_state(n, prec):
     """FP64: pointwise at sampled grid points.  FP32: the rounding of P ~ 2 to
     FP32 is white noise over every mode up to K, and the divergence multiplies
@@ -157,7 +176,7 @@ def test_rhs_exact_lowmode_state(n, prec):
     dt_ = torch.float64 if prec == "fp64" else torch.float32
     Un = torch.empty((8, n, n, n), dtype=dt_, device="cuda:0")
     for f in range(8):
-        Un[f] = torch.from_numpy(upsample_field(U0[f], n)).to("cuda:0", dtype=dt_)
+        Un[f] = upsample_field_gpu(U0[f], n).to(dt_)
     S = solver(n, prec, gamma=gamma, nu=nu, eta=eta)
     out = S.rhs(Un)
     del Un
