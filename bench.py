@@ -14,6 +14,13 @@ nu = eta = 2e-3, dt from CFL 0.1.  A secondary 512^3 ABC-dynamo line
 the batched ensemble (64 runs of 32^3..128^3 in one graph per step) against
 the same runs advanced one after another under "ensemble".
 
+Per precision: warm-up steps, then a few steps with every launch class
+bracketed by HIP events (the per-pass table "passes", and which class
+dominates), then the timed steps, during which only the dominant class's
+launches are bracketed (its per-launch time gives "roofline"); each event pair
+costs a few microseconds between launches, 5% of a 256^3 step if every launch
+had one.
+
 Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
 build runs on one GPU.
 """
@@ -85,12 +92,15 @@ def describe(case) -> str:
 FIELDS = ("rho", "m_x", "m_y", "m_z", "B_x", "B_y", "B_z", "E")
 
 
-def timed_run(case, precision: str, steps: int, warmup: int, diag_every: int = 10):
-    """warmup + timed steps of one precision; returns timings, profile and the
-    final state (FP64 host copy is not made: the state stays on the GPU)."""
+def timed_run(case, precision: str, steps: int, warmup: int, diag_every: int = 10, prof_steps: int = 10):
+    """warmup steps; prof_steps steps with every launch class bracketed by HIP
+    events (the per-pass table, and which class dominates); then the timed
+    steps, with events around the dominant class's launches only (each event
+    pair costs a few microseconds between launches).  The state stays on the
+    GPU; `total_steps` counts every step taken."""
     import torch
 
-    from paper_1810_12707_amd.mhd import Solver
+    from paper_1810_12707_amd.mhd import PASS_NAMES, Solver
 
     dev = torch.device("cuda:0")
     U64 = torch.from_numpy(case.U).to(dev)
@@ -99,8 +109,13 @@ def timed_run(case, precision: str, steps: int, warmup: int, diag_every: int = 1
     del U64
     for _ in range(warmup):
         S.step(1)
-    torch.cuda.synchronize()
     S.profile(True)
+    S.step(prof_steps)
+    prof_all = S.profile_read()
+    S.profile(False)
+    dom = max((k for k in PASS_NAMES if prof_all[k]["launches"] > 0), key=lambda k: prof_all[k]["ms"])
+    torch.cuda.synchronize()
+    S.profile([dom])
     stream = torch.cuda.current_stream(dev)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -116,10 +131,11 @@ def timed_run(case, precision: str, steps: int, warmup: int, diag_every: int = 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    prof = S.profile_read()
+    prof_dom = S.profile_read()
     S.profile(False)
     rc_end, diag = S.diagnostics()
-    out = {"ms": ms, "wall_s": wall, "prof": prof, "diag": diag, "rc": (rc_diag, rc_end),
+    out = {"ms": ms, "wall_s": wall, "prof": prof_all, "prof_steps": prof_steps, "prof_dom": prof_dom,
+           "dominant": dom, "diag": diag, "rc": (rc_diag, rc_end), "total_steps": warmup + prof_steps + steps,
            "step_bytes": S.step_bytes, "ws_bytes": S.workspace.numel(), "state": S.get_state(torch.float64)}
     S.close()
     del S
@@ -154,7 +170,7 @@ def rel_errors(a, ref):
 def run_gpu(case, steps: int, warmup: int, with_fp64_error: bool = True, with_mixed: bool = True):
     r = timed_run(case, "fp32", steps, warmup)
     mixed = timed_run(case, "mixed", steps, warmup) if with_mixed else None
-    ref = fp64_state(case, warmup + steps) if with_fp64_error else None
+    ref = fp64_state(case, r["total_steps"]) if with_fp64_error else None
     r["err_vs_fp64"] = rel_errors(r["state"], ref) if ref is not None else None
     if mixed is not None:
         mixed["err_vs_fp64"] = rel_errors(mixed["state"], ref) if ref is not None else None
@@ -172,23 +188,22 @@ def mixed_line(m, n, steps):
             "ms_per_step": round(m["ms"] / steps, 5), "err_vs_fp64": m["err_vs_fp64"], "status": m["rc"],
             "step_hbm": {"GBps": round(m["step_bytes"] / (sec / steps) / 1e9, 1),
                          "frac": round(m["step_bytes"] / (sec / steps) / 1e9 / HBM_PEAK_GBS, 4)},
-            "passes": pass_table(m["prof"], steps),
+            "passes": pass_table(m["prof"], m["prof_steps"]),
             "what": "FP32 data; radix-16 FFT stages as split-BF16x3 MFMA products, FP32 accumulate"}
 
 
-def roofline_from(prof: dict, traffic: dict | None):
-    passes = {k: v for k, v in prof.items() if k in PASS_NAMES and v["launches"] > 0}
-    dom = max(passes, key=lambda k: passes[k]["ms"])
-    p = passes[dom]
+def roofline_from(prof_dom: dict, dom: str, traffic: dict | None):
+    """The dominant class's events from the timed region (prof_dom)."""
+    p = prof_dom[dom]
     per_launch_bytes = p["bytes"] / p["launches"]
     per_launch_ms = p["ms"] / p["launches"]
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     t = None
     if traffic and dom in traffic:
         t = traffic[dom]
-    return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": t, "kernel": PASS_KERNELS[dom],
-                 "bytes_per_launch": per_launch_bytes, "ms_per_launch": round(per_launch_ms, 5)}
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": t, "kernel": PASS_KERNELS[dom],
+            "bytes_per_launch": per_launch_bytes, "ms_per_launch": round(per_launch_ms, 5)}
 
 
 def pass_table(prof: dict, steps: int):
@@ -343,7 +358,8 @@ def main(argv=None):
     n = case.n
     sec = r["ms"] * 1e-3
     value = n ** 3 * a.steps / sec
-    dom, roof = roofline_from(r["prof"], load_traffic(n))
+    dom = r["dominant"]
+    roof = roofline_from(r["prof_dom"], dom, load_traffic(n))
     step_gbs = r["step_bytes"] / (sec / a.steps) / 1e9
     log(f"[bench] {r['ms'] / a.steps:.4f} ms/step, {value:.4e} pt-steps/s; dominant {dom} {roof['achieved']} GB/s")
     workload = describe(case)
@@ -355,7 +371,7 @@ def main(argv=None):
         c2 = make_case(a.secondary)
         r2 = run_gpu(c2, a.secondary_steps, 3, with_fp64_error=not a.no_fp64_error, with_mixed=not a.no_mixed)
         s2 = r2["ms"] * 1e-3
-        dom2, roof2 = roofline_from(r2["prof"], load_traffic(c2.n))
+        roof2 = roofline_from(r2["prof_dom"], r2["dominant"], load_traffic(c2.n))
         secondary = {
             "workload": describe(c2), "value": c2.n ** 3 * a.secondary_steps / s2, "unit": "grid-point-steps/s",
             "ms_per_step": round(r2["ms"] / a.secondary_steps, 4), "steps": a.secondary_steps,
@@ -363,7 +379,7 @@ def main(argv=None):
             "step_hbm": {"alg_bytes_per_step": r2["step_bytes"],
                          "GBps": round(r2["step_bytes"] / (s2 / a.secondary_steps) / 1e9, 1),
                          "frac": round(r2["step_bytes"] / (s2 / a.secondary_steps) / 1e9 / HBM_PEAK_GBS, 4)},
-            "passes": pass_table(r2["prof"], a.secondary_steps),
+            "passes": pass_table(r2["prof"], r2["prof_steps"]),
             "err_vs_fp64": r2["err_vs_fp64"], "status": r2["rc"],
             "mixed_path": mixed_line(r2["mixed"], c2.n, a.secondary_steps),
         }
@@ -400,7 +416,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "step_hbm": {"alg_bytes_per_step": r["step_bytes"], "GBps": round(step_gbs, 1),
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
-        "passes": pass_table(r["prof"], a.steps),
+        "passes": pass_table(r["prof"], r["prof_steps"]),
         "err_vs_fp64": r["err_vs_fp64"],
         "mixed_path": mixed_line(r["mixed"], n, a.steps),
         "status": r["rc"],

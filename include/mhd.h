@@ -173,12 +173,15 @@ enum {
     MHD_PASS_RHO, MHD_PASS_REDUCE, MHD_PASS_COUNT
 };
 
-/* Benchmark hook (not physics): enable = 1 clears the counters and brackets
- * every later kernel launch of mhd_step with a pair of HIP events on the
- * context's stream (at most 4096 launches are recorded; later ones are
- * counted as dropped); enable = 0 stops recording.  Creates its events on
- * first use (no device memory). */
-int mhd_profile(mhd_ctx* ctx, int32_t enable);
+/* Benchmark hook (not physics).  class_mask != 0 clears the counters and
+ * brackets every later kernel launch of mhd_step whose launch class cls has
+ * bit (1 << cls) set in class_mask with a pair of HIP events on the
+ * context's stream (-1 selects every class; at most 4096 launches are
+ * recorded, later ones are counted as dropped); class_mask = 0 stops
+ * recording.  Each event pair adds a little time between launches, so a
+ * throughput measurement should select only the classes it needs.  Creates
+ * its events on first use (no device memory). */
+int mhd_profile(mhd_ctx* ctx, int32_t class_mask);
 
 /* Synchronises the stream and writes, per launch class (MHD_PASS_*), the
  * summed kernel time in milliseconds, the number of launches timed and the

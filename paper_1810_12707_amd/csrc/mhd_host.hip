@@ -266,6 +266,7 @@ struct mhd_ctx {
   std::string last_err;
   // benchmark timing (mhd_profile)
   bool prof_on = false;
+  uint32_t prof_mask = 0;     // launch classes bracketed with events (bit cls)
   std::vector<hipEvent_t> ev;  // 2 per recorded launch
   std::vector<int> rec_cls;
   std::vector<double> rec_bytes;
@@ -381,7 +382,8 @@ struct Engine {
   // Runs `launch`; while profiling, brackets it with a pair of events.
   template <typename F>
   void timed(int cls, F&& launch) {
-    if (c->prof_on && c->nrec < (int)c->rec_cls.size()) {
+    const bool want = c->prof_on && ((c->prof_mask >> cls) & 1u);
+    if (want && c->nrec < (int)c->rec_cls.size()) {
       const int r = c->nrec++;
       (void)hipEventRecord(c->ev[2 * r], c->stream);
       launch();
@@ -389,7 +391,7 @@ struct Engine {
       c->rec_cls[r] = cls;
       c->rec_bytes[r] = class_bytes(cls);
     } else {
-      if (c->prof_on) ++c->dropped;
+      if (want) ++c->dropped;
       launch();
     }
   }
@@ -1177,9 +1179,9 @@ int mhd_fft3d(mhd_ctx* c, int32_t dir, const void* d_in, void* d_out) {
   });
 }
 
-int mhd_profile(mhd_ctx* c, int32_t enable) {
+int mhd_profile(mhd_ctx* c, int32_t class_mask) {
   if (!c) return MHD_E_ARG;
-  if (enable) {
+  if (class_mask) {
     constexpr int kCap = 4096;
     if (c->ev.empty()) {
       c->ev.resize(2 * kCap);
@@ -1193,7 +1195,8 @@ int mhd_profile(mhd_ctx* c, int32_t enable) {
     c->nrec = 0;
     c->dropped = 0;
   }
-  c->prof_on = enable != 0;
+  c->prof_on = class_mask != 0;
+  c->prof_mask = (uint32_t)class_mask;
   return MHD_OK;
 }
 

@@ -224,8 +224,15 @@ def mhd_fft3d(ctx, direction: int, x_in, x_out):
         "mhd_fft3d", ctx)
 
 
-def mhd_profile(ctx, enable: bool):
-    _rc(lib().mhd_profile(ctx, 1 if enable else 0), "mhd_profile", ctx)
+PROFILE_ALL = -1
+
+
+def mhd_profile(ctx, class_mask):
+    """class_mask: bit (1 << i) records launch class PASS_NAMES[i]; True or -1
+    records every class; False or 0 stops recording."""
+    if class_mask is True:
+        class_mask = PROFILE_ALL
+    _rc(lib().mhd_profile(ctx, int(class_mask)), "mhd_profile", ctx)
 
 
 def mhd_profile_read(ctx) -> dict:
@@ -389,6 +396,9 @@ class Solver:
         return out
 
     def profile(self, enable=True):
+        """enable: True (every launch class), False, a bit mask, or a list of pass names."""
+        if isinstance(enable, (list, tuple)):
+            enable = sum(1 << PASS_NAMES.index(name) for name in enable)
         mhd_profile(self.ctx, enable)
 
     def profile_read(self) -> dict:
