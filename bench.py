@@ -144,7 +144,8 @@ def timed_run(case, precision: str, steps: int, warmup: int, diag_every: int = 1
 
 
 def fp64_state(case, nsteps: int):
-    """The FP64 GPU run of the same start, same number of steps."""
+    """The FP64 GPU run of the same start, same number of steps: its state and
+    diagnostics."""
     import torch
 
     from paper_1810_12707_amd.mhd import Solver
@@ -154,10 +155,28 @@ def fp64_state(case, nsteps: int):
     D.set_state(torch.from_numpy(case.U).to(dev))
     D.step(nsteps)
     st = D.get_state(torch.float64)
+    _, diag = D.diagnostics()
     D.close()
     del D
     torch.cuda.empty_cache()
-    return st
+    return st, diag
+
+
+DIAG_KEYS = ("mass", "e_kin", "e_mag", "e_int", "e_tot", "h_cross", "h_mag", "divb_rms", "j_rms", "dt_cfl")
+
+
+def diag_errors(d, ref):
+    """Relative differences of the FP64-reduced diagnostics from those of the
+    FP64 run (div B in units of the rms current density; absolute for
+    quantities that vanish in the reference)."""
+    out = {}
+    for k in DIAG_KEYS:
+        a, b = float(d[k]), float(ref[k])
+        if k == "divb_rms":  # rounding-level in both: compare in units of the current density
+            out[k] = abs(a - b) / float(ref["j_rms"])
+        else:
+            out[k] = abs(a - b) / abs(b) if abs(b) > 1e-300 else abs(a - b)
+    return out
 
 
 def rel_errors(a, ref):
@@ -170,10 +189,12 @@ def rel_errors(a, ref):
 def run_gpu(case, steps: int, warmup: int, with_fp64_error: bool = True, with_mixed: bool = True):
     r = timed_run(case, "fp32", steps, warmup)
     mixed = timed_run(case, "mixed", steps, warmup) if with_mixed else None
-    ref = fp64_state(case, r["total_steps"]) if with_fp64_error else None
+    ref, ref_diag = fp64_state(case, r["total_steps"]) if with_fp64_error else (None, None)
     r["err_vs_fp64"] = rel_errors(r["state"], ref) if ref is not None else None
+    r["diag_err_vs_fp64"] = diag_errors(r["diag"], ref_diag) if ref is not None else None
     if mixed is not None:
         mixed["err_vs_fp64"] = rel_errors(mixed["state"], ref) if ref is not None else None
+        mixed["diag_err_vs_fp64"] = diag_errors(mixed["diag"], ref_diag) if ref is not None else None
         del mixed["state"]
     del r["state"], ref
     r["mixed"] = mixed
@@ -185,7 +206,8 @@ def mixed_line(m, n, steps):
         return None
     sec = m["ms"] * 1e-3
     return {"value": round(n ** 3 * steps / sec, 1), "unit": "grid-point-steps/s",
-            "ms_per_step": round(m["ms"] / steps, 5), "err_vs_fp64": m["err_vs_fp64"], "status": m["rc"],
+            "ms_per_step": round(m["ms"] / steps, 5), "err_vs_fp64": m["err_vs_fp64"],
+            "diag_err_vs_fp64": m["diag_err_vs_fp64"], "status": m["rc"],
             "step_hbm": {"GBps": round(m["step_bytes"] / (sec / steps) / 1e9, 1),
                          "frac": round(m["step_bytes"] / (sec / steps) / 1e9 / HBM_PEAK_GBS, 4)},
             "passes": pass_table(m["prof"], m["prof_steps"]),
@@ -380,7 +402,7 @@ def main(argv=None):
                          "GBps": round(r2["step_bytes"] / (s2 / a.secondary_steps) / 1e9, 1),
                          "frac": round(r2["step_bytes"] / (s2 / a.secondary_steps) / 1e9 / HBM_PEAK_GBS, 4)},
             "passes": pass_table(r2["prof"], r2["prof_steps"]),
-            "err_vs_fp64": r2["err_vs_fp64"], "status": r2["rc"],
+            "err_vs_fp64": r2["err_vs_fp64"], "diag_err_vs_fp64": r2["diag_err_vs_fp64"], "status": r2["rc"],
             "mixed_path": mixed_line(r2["mixed"], c2.n, a.secondary_steps),
         }
         log(f"[bench] secondary {secondary['ms_per_step']} ms/step")
@@ -418,6 +440,7 @@ def main(argv=None):
                      "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "passes": pass_table(r["prof"], r["prof_steps"]),
         "err_vs_fp64": r["err_vs_fp64"],
+        "diag_err_vs_fp64": r["diag_err_vs_fp64"],
         "mixed_path": mixed_line(r["mixed"], n, a.steps),
         "status": r["rc"],
         "wall_s": round(r["wall_s"], 4),
