@@ -250,13 +250,91 @@ __device__ __forceinline__ bool first_slot(int tid, int i, int& b, int& j) {
   }
 }
 
-// LDS element address of (sequence b, position pos).  PADSH > 0 inserts one
-// padding slot after every 2^PADSH positions, which spreads the strided
-// Stockham writes of row-major sequences over the LDS banks.
+// Layout code of an LDS sequence buffer (the PADSH template argument of the
+// functions below): bits 0-3 give the padding shift s -- one padding slot
+// after every 2^s positions, which spreads the strided Stockham writes of
+// row-major sequences over the LDS banks (0: no padding) -- and kLinear asks
+// for linear addressing (see slot_map).
+constexpr int kLinear = 16;
+template <int PADSH> constexpr int pad_shift() { return PADSH & 15; }
+template <int PADSH> constexpr bool linear_addr() { return (PADSH & kLinear) != 0; }
+
+// LDS element address of (sequence b, position pos).
 template <int ES, int BS, int PADSH>
 __device__ __forceinline__ int lds_at(int b, int pos) {
-  if constexpr (PADSH > 0) return b * BS + pos * ES + (pos >> PADSH);
+  constexpr int PS = pad_shift<PADSH>();
+  if constexpr (PS > 0) return b * BS + pos * ES + (pos >> PS);
   else return b * BS + pos * ES;
+}
+
+// LDS read that the compiler may not pair with a neighbour into one ds_read2
+// instruction: on gfx950 a ds_read2_b64 keeps the LDS busy four times as long
+// as a ds_read_b64 (half the read bandwidth), while pairing writes costs
+// nothing.  Used where linear addressing puts reads at base + immediate.
+template <typename X> __device__ __forceinline__ X lds_rd(const X* p) {
+  X v = *p;
+  asm volatile("" ::: "memory");
+  return v;
+}
+
+// True when the twiddle index k = j mod NS of a pass is the same in every slot
+// w = tid + i NT of a thread (lane_map MAP over NB sequences of NBF
+// butterflies): MAP 1 gives j = w mod NBF and NS divides NBF, MAP 0 gives
+// j = w / NB.  The thread then reads its R - 1 twiddles once per pass.
+template <int MAP, int NB, int NBF, int NT, int NS> constexpr bool slot_invariant_k() {
+  if (MAP == 1) return NT % NS == 0;
+  if (MAP == 0) return NT % NB == 0 && (NT / NB) % NS == 0;
+  return false;
+}
+
+// Twiddles t[r] = tw[k r N/(NS R)], r = 1..R-1, of butterfly j (k = j mod NS).
+template <typename T, int N, int R, int NS>
+__device__ __forceinline__ void load_pass_twiddles(cx<T> (&t)[R], const cx<T>* tw, int j) {
+  const int k = j % NS;
+#pragma unroll
+  for (int r = 1; r < R; ++r) t[r] = tw[k * r * (N / (NS * R))];
+}
+
+// (sequence b, butterfly j) of slot i of thread tid: lane_map on
+// w = tid + i NT.  Linear addressing (LIN): when NT is a multiple of the
+// faster-running index's range the slots differ only in the slower index, by
+// a constant step; that is written out so that LDS addresses become one base
+// plus immediate offsets, which saves the address registers of every slot and
+// radix element (at N = 512 the mixed-precision flux pass spilled without
+// it).  Without LIN the compiler keeps one precomputed address per element,
+// and its reads stay single ds_read_b64s.
+template <int NB, int NBF, int NT, int MAP, bool LIN = true>
+__device__ __forceinline__ void slot_map(int tid, int i, int& b, int& j) {
+  if constexpr (LIN && MAP == 1 && NT % NBF == 0) {
+    b = tid / NBF + i * (NT / NBF);
+    j = tid % NBF;
+  } else if constexpr (LIN && MAP == 0 && NT % NB == 0) {
+    b = tid % NB;
+    j = tid / NB + i * (NT / NB);
+  } else {
+    lane_map<NB, NBF, MAP>(tid + i * NT, b, j);
+  }
+}
+
+// With linear addressing: the LDS address step from position p to p + STEP
+// when it is the same for every p (no padding, or STEP a multiple of the
+// padding period); 0 otherwise, and always 0 without linear addressing.
+template <int ES, int PADSH, int STEP> constexpr int lds_step() {
+  constexpr int PS = pad_shift<PADSH>();
+  if (!linear_addr<PADSH>()) return 0;
+  if (PS == 0) return STEP * ES;
+  if (STEP % (1 << PS) == 0) return STEP * ES + (STEP >> PS);
+  return 0;
+}
+
+// Step between the R output positions d + r NS of a Stockham butterfly
+// (d = (j / NS) NS R + j mod NS).  In a first pass (NS = 1) d is a multiple of
+// R, so when R divides the padding period the R outputs share one padding
+// slot count and the step is ES.
+template <int ES, int PADSH, int NS, int R> constexpr int lds_write_step() {
+  constexpr int PS = pad_shift<PADSH>();
+  if (linear_addr<PADSH>() && NS == 1 && PS > 0 && (1 << PS) % R == 0) return ES;
+  return lds_step<ES, PADSH, NS>();
 }
 
 // One VALU Stockham pass.  NB sequences, NT threads; B_ACT (<= NB) of them active.
@@ -268,22 +346,39 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
   constexpr int NBF = N / R;
   constexpr int TOT = NB * NBF;
   constexpr int CNT = (TOT + NT - 1) / NT;
+  constexpr bool TWS = NS > 1 && CNT > 1 && slot_invariant_k<MAP, NB, NBF, NT, NS>();
+  constexpr int RSTEP = lds_step<ES, PADSH, NBF>();
+  constexpr int WSTEP = lds_write_step<ES, PADSH, NS, R>();
+  cx<T> tws[R];
+  if constexpr (TWS) {
+    int b0, j0;
+    slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, 0, b0, j0);
+    load_pass_twiddles<T, N, R, NS>(tws, tw, j0);
+  }
   cx<T> v[CNT][R];
 #pragma unroll
   for (int i = 0; i < CNT; ++i) {
-    const int w = tid + i * NT;
     int b, j;
-    lane_map<NB, NBF, MAP>(w, b, j);
-    if ((TOT % NT == 0 || w < TOT) && b < b_act) {
+    slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
+    if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
+      if constexpr (RSTEP > 0) {
+        const int a0 = lds_at<ES, BS, PADSH>(b, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
+        for (int r = 0; r < R; ++r) v[i][r] = lds_rd(&buf[a0 + r * RSTEP]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
+      }
       if constexpr (NS > 1) {
-        const int k = j % NS;
+        cx<T> t[R];
+        if constexpr (TWS) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          const cx<T> t = tw[k * r * (N / (NS * R))];
-          v[i][r] = (S < 0) ? cmul(v[i][r], t) : cmulc(v[i][r], t);
+          for (int r = 1; r < R; ++r) t[r] = tws[r];
+        } else {
+          load_pass_twiddles<T, N, R, NS>(t, tw, j);
         }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = (S < 0) ? cmul(v[i][r], t[r]) : cmulc(v[i][r], t[r]);
       }
       dft<R, S>(v[i]);
     }
@@ -291,14 +386,19 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < CNT; ++i) {
-    const int w = tid + i * NT;
     int b, j;
-    lane_map<NB, NBF, MAP>(w, b, j);
-    if ((TOT % NT == 0 || w < TOT) && b < b_act) {
+    slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
+    if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
       const int k = j % NS;
       const int d = (j / NS) * NS * R + k;
+      if constexpr (WSTEP > 0) {
+        const int a0 = lds_at<ES, BS, PADSH>(b, d);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_at<ES, BS, PADSH>(b, d + r * NS)] = v[i][r];
+        for (int r = 0; r < R; ++r) buf[a0 + r * WSTEP] = v[i][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lds_at<ES, BS, PADSH>(b, d + r * NS)] = v[i][r];
+      }
     }
   }
   __syncthreads();
@@ -470,6 +570,72 @@ __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const floa
   }
 }
 
+// Positions r NBF .. r NBF + NBF - 1 of output row r lie strictly between
+// KEEP and N - KEEP (bit r set): outputs a caller does not want when KEEP > 0.
+template <int N, int NBF, int R, int KEEP> constexpr unsigned gap_rows() {
+  unsigned m = 0;
+  if (KEEP > 0)
+    for (int r = 0; r < R; ++r)
+      if (r * NBF > KEEP && r * NBF + NBF - 1 < N - KEEP) m |= 1u << r;
+  return m;
+}
+
+// Last VALU pass of a plan.  Butterfly j of sequence b reads positions
+// j + r NBF and, since NS = NBF in the last pass, its outputs belong at those
+// same positions.  INPLACE: they are written back there (no barrier needed in
+// between; store is not called); otherwise they go to
+// store(i, r, b, j + r NBF, value).  KEEP > 0: positions strictly between KEEP
+// and N - KEEP are not wanted; the output rows r that lie wholly there are
+// neither computed nor stored.
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, int KEEP, bool INPLACE,
+          class Store>
+__device__ __forceinline__ void fft_last_valu(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Store&& store) {
+  constexpr int N = PL::N;
+  constexpr int P = PL::np - 1;
+  constexpr int R = PL::r[P];
+  constexpr int NBF = N / R;
+  constexpr int TOT = NB * NBF;
+  constexpr int CNT = (TOT + NT - 1) / NT;
+  constexpr unsigned GAP = gap_rows<N, NBF, R, KEEP>();
+  constexpr bool TWS = CNT > 1 && slot_invariant_k<MAP, NB, NBF, NT, NBF>();
+  constexpr int RSTEP = lds_step<ES, PADSH, NBF>();
+  cx<T> tws[R];
+  if constexpr (TWS) {
+    int b0, j0;
+    slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, 0, b0, j0);
+    load_pass_twiddles<T, N, R, NBF>(tws, tw, j0);
+  }
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
+    int b, j;
+    slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
+    if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
+      cx<T> v[R], t[R];
+      const int a0 = lds_at<ES, BS, PADSH>(b, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if constexpr (RSTEP > 0) v[r] = lds_rd(&buf[a0 + r * RSTEP]);
+        else v[r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
+      }
+      if constexpr (TWS) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) t[r] = tws[r];
+      } else {
+        load_pass_twiddles<T, N, R, NBF>(t, tw, j);  // k = j in the last pass
+      }
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = (S < 0) ? cmul(v[r], t[r]) : cmulc(v[r], t[r]);
+      dft<R, S>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if ((GAP >> r) & 1u) continue;
+        if constexpr (INPLACE) buf[RSTEP > 0 ? a0 + r * RSTEP : lds_at<ES, BS, PADSH>(b, j + r * NBF)] = v[r];
+        else store(i, r, b, j + r * NBF, v[r]);
+      }
+    }
+  }
+}
+
 template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP = 0, int PADSH = 0>
 __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   if constexpr (PL::MX && PL::r[P] == 16) {
@@ -481,8 +647,12 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
   }
 }
 
-// All passes LDS to LDS (an MFMA last pass runs in place, group by group).
-template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, int P = 0>
+// All passes LDS to LDS; the last pass runs in place (butterfly by butterfly
+// on the VALU, group by group on the MFMA units) and is followed by a barrier.
+// KEEP > 0: only positions <= KEEP and >= N - KEEP of the result are wanted
+// (the others may be left stale).
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, int KEEP = 0,
+          int P = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   static_assert(plan_ok<PL>(), "radix plan does not multiply to N");
   if constexpr (P < PL::np) {
@@ -492,9 +662,13 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, in
           fb, reinterpret_cast<const float2*>(tw), tid, b_act,
           [&](int, int, int b, int pos, float2 v) { fb[lds_at<ES, BS, PADSH>(b, pos)] = v; });
       __syncthreads();
+    } else if constexpr (P == PL::np - 1 && P > 0) {
+      fft_last_valu<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, true>(buf, tw, tid, b_act,
+                                                                       [](int, int, int, int, cx<T>) {});
+      __syncthreads();
     } else {
       fft_pass<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
-      lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, P + 1>(buf, tw, tid, b_act);
+      lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, P + 1>(buf, tw, tid, b_act);
     }
   }
 }
@@ -572,8 +746,11 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
 #pragma unroll
         for (int r = 0; r < FP::R; ++r) store(i, r, b, r, v[i][r]);
       } else {
+        constexpr int WSTEP = lds_write_step<ES, PADSH, 1, FP::R>();
+        const int a0 = lds_at<ES, BS, PADSH>(b, j * FP::R);
 #pragma unroll
-        for (int r = 0; r < FP::R; ++r) buf[lds_at<ES, BS, PADSH>(b, j * FP::R + r)] = v[i][r];
+        for (int r = 0; r < FP::R; ++r)
+          buf[WSTEP > 0 ? a0 + r * WSTEP : lds_at<ES, BS, PADSH>(b, j * FP::R + r)] = v[i][r];
       }
     }
   }
@@ -584,18 +761,17 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
 // store(i, r, b, pos, value) with pos = j + r N/R for the thread's i-th
 // butterfly j.  On the VALU the last pass computes straight into registers;
 // an MFMA last pass writes LDS and the same (i, r, pos) are then read back.
+// INPLACE: a VALU last pass writes its outputs back to the LDS positions it
+// read instead of calling store (which must then write LDS position pos of
+// sequence b, as it is still called by an MFMA last pass).
 template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, bool SLOTS = false,
-          class Store>
+          bool INPLACE = false, class Store>
 __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Store&& store) {
   constexpr int NP = PL::np;
   if constexpr (NP > 1) {
     fft_mid_passes<T, PL, NB, NT, ES, BS, S, MAP, PADSH, 1>(buf, tw, tid, b_act);
     constexpr int PLAST = NP - 1;
     constexpr int R = PL::r[PLAST];
-    constexpr int NS = plan_ns<PL>(PLAST);  // = N / R
-    constexpr int NBF = PL::N / R;
-    constexpr int TOT = NB * NBF;
-    constexpr int CNT = (TOT + NT - 1) / NT;
     if constexpr (PL::MX && R == 16) {
       auto st2 = [&](int i, int r, int b, int pos, float2 v) {
         cx<T> vv;
@@ -606,25 +782,7 @@ __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, i
       fft_pass_mfma_last<PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH, decltype(st2)&, SLOTS>(
           reinterpret_cast<const float2*>(buf), reinterpret_cast<const float2*>(tw), tid, b_act, st2);
     } else {
-#pragma unroll
-      for (int i = 0; i < CNT; ++i) {
-        const int w = tid + i * NT;
-        int b, j;
-        lane_map<NB, NBF, MAP>(w, b, j);
-        if ((TOT % NT == 0 || w < TOT) && b < b_act) {
-          cx<T> v[R];
-#pragma unroll
-          for (int r = 0; r < R; ++r) v[r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
-#pragma unroll
-          for (int r = 1; r < R; ++r) {
-            const cx<T> t = tw[j * r];  // k = j mod NS = j; index k r N/(NS R) = j r
-            v[r] = (S < 0) ? cmul(v[r], t) : cmulc(v[r], t);
-          }
-          dft<R, S>(v);
-#pragma unroll
-          for (int r = 0; r < R; ++r) store(i, r, b, j + r * NS, v[r]);
-        }
-      }
+      fft_last_valu<T, PL, NB, NT, ES, BS, S, MAP, PADSH, 0, INPLACE>(buf, tw, tid, b_act, store);
     }
   }
 }

@@ -466,12 +466,17 @@ template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
   return (sizeof(T) == 4 && N >= 1024) ? 2 * kThreads : kThreads;
 }
 
-// The MFMA variant is held to two waves per SIMD: left free, the flux pass
-// took more than 256 registers at N = 512 and ran one wave per SIMD, 1.3x
-// slower than capped with a small spill.
+// FP32 row passes (MFMA variant included) are held to two waves per SIMD,
+// which is what their LDS allows: left free, the flux pass can take more than
+// 256 registers and then runs one wave per SIMD (the MFMA variant at N = 512
+// was 1.3x slower so than capped with a small spill).
+template <typename T, int N, int MODE, bool MX> constexpr int row_min_blocks() {
+  return sizeof(T) == 4 ? 2 * kThreads / row_threads<T, N, MODE, MX>() : 1;
+}
+
 template <typename T, int N, int MODE, bool MX>
-__global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()),
-                                  (MX ? 2 * kThreads / row_threads<T, N, MODE, MX>() : 1)) k_row(const RowArgs<T> a) {
+__global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_blocks<T, N, MODE, MX>()))
+    k_row(const RowArgs<T> a) {
   using PL = PlanOf<N, MX>;
   constexpr int NT = row_threads<T, N, MODE, MX>();
   constexpr int K = Band<N>::K, NHP = Band<N>::NHP;
@@ -479,9 +484,15 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()),
   constexpr int NB = RowShape<MODE>::NB;
   constexpr int PADSH = 3;                    // one LDS padding slot per 8 elements
   constexpr int BS = N + (N >> PADSH) + 1;   // padded row pitch in LDS
+  // Linear LDS addressing where the precomputed addresses would push a pass
+  // past 256 registers into spills (the flux pass from N = 512 mixed and
+  // N = 1024 FP32, the diagnostics pass at N = 1024); elsewhere they fit and
+  // were measured a little faster.
+  constexpr bool LIN = (MODE == RM_XB && N >= (MX ? 512 : 1024)) || (MODE == RM_XDIAG && N >= 1024);
+  constexpr int LAY = PADSH | (LIN ? kLinear : 0);
   constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
   using FP = FirstPass<PL, NB, NT>;
-  auto at = [](int b, int pos) { return lds_at<1, BS, PADSH>(b, pos); };
+  auto at = [](int b, int pos) { return lds_at<1, BS, LAY>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
@@ -634,9 +645,9 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()),
           v[i][r] = z;
         }
       }
-      fft_first_regs<T, PL, NB, NT, 1, BS, +1, (FMAP == 2 ? 2 : 1), PADSH>(buf, v, tid, nin, lds_store);
+      fft_first_regs<T, PL, NB, NT, 1, BS, +1, (FMAP == 2 ? 2 : 1), LAY>(buf, v, tid, nin, lds_store);
       if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
-      fft_rest<T, PL, NB, NT, 1, BS, +1, 1, PADSH>(buf, stw, tid, nin, lds_store);
+      fft_rest<T, PL, NB, NT, 1, BS, +1, 1, LAY, false, true>(buf, stw, tid, nin, lds_store);
     }
     __syncthreads();
 
@@ -770,7 +781,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()),
 
     if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
       __syncthreads();
-      lds_fft<T, PL, NB, NT, 1, BS, -1, 1, PADSH>(buf, stw, tid, nout);
+      lds_fft<T, PL, NB, NT, 1, BS, -1, 1, LAY, K>(buf, stw, tid, nout);  // only k <= K and N - k are read
       // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
       T* out0 = member_ptr(a.out0, mem, a.bt.mstride);
       const int64_t ost = a.out_stride;
