@@ -253,24 +253,63 @@ __device__ __forceinline__ bool first_slot(int tid, int i, int& b, int& j) {
 // Layout code of an LDS sequence buffer (the PADSH template argument of the
 // functions below): bits 0-3 give the padding shift s -- one padding slot
 // after every 2^s positions, which spreads the strided Stockham writes of
-// row-major sequences over the LDS banks (0: no padding) -- and kLinear asks
-// for linear addressing (see slot_map).
+// row-major sequences over the LDS banks (0: no padding); kLinear asks for
+// linear addressing (see slot_map); kSwizzle for the stage swizzle below
+// (without padding).
 constexpr int kLinear = 16;
-template <int PADSH> constexpr int pad_shift() { return PADSH & 15; }
+constexpr int kSwizzle = 32;
+template <int PADSH> constexpr int pad_shift() { return (PADSH & kSwizzle) ? 0 : (PADSH & 15); }
 template <int PADSH> constexpr bool linear_addr() { return (PADSH & kLinear) != 0; }
+template <int PADSH> constexpr bool swizzled() { return (PADSH & kSwizzle) != 0; }
 
-// LDS element address of (sequence b, position pos).
-template <int ES, int BS, int PADSH>
+constexpr bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// Stage swizzle.  Measured on gfx950, a wave's ds_read_b64 is served 32 lanes
+// per cycle over 64 four-byte banks and its ds_write_b64 16 lanes per cycle
+// over 32, so a read is conflict-free when its 32 lanes hit distinct
+// positions mod 32 and a write when its 16 lanes hit distinct positions mod 16
+// (8-byte elements).  Padding one slot per 8 positions serves the strided
+// Stockham writes but costs every contiguous access a second cycle.  Instead,
+// position p of a sequence is stored at p ^ f(p >> 4) (f < 16, so every
+// aligned 16-block is permuted in place and contiguous accesses stay
+// conflict-free), with f chosen per stage -- the array that pass s - 1
+// writes and pass s reads; stage 0, the transform's input, shares the last
+// stage's layout -- to spread the writes of pass s - 1: with NS = product of
+// the radices before it and R its radix (both powers of two, NS < 16), the 16
+// lanes of a write cover 16 / NS butterfly groups, and f gives each group
+// its own value in bits log2(NS) .. 3.
+template <class PL, int STG> __device__ __forceinline__ int stage_swz(int row) {
+  constexpr int st = (STG == 0 || STG >= PL::np) ? PL::np - 1 : STG;
+  if constexpr (st == 0) {
+    return 0;
+  } else {
+    constexpr int NSW = plan_ns<PL>(st - 1), RW = PL::r[st - 1];
+    if constexpr (NSW >= 16 || !is_pow2(NSW) || !is_pow2(RW) || PL::N % 16 != 0) {
+      return 0;
+    } else if constexpr (NSW * RW >= 16) {
+      return ((row / (NSW * RW / 16)) % (16 / NSW)) << ilog2(NSW);
+    } else {
+      return (row % RW) << ilog2(NSW);
+    }
+  }
+}
+
+// LDS element address of (sequence b, position pos) in stage STG of plan PL
+// (the stage matters only to a swizzled layout).
+template <int ES, int BS, int PADSH, class PL = void, int STG = 0>
 __device__ __forceinline__ int lds_at(int b, int pos) {
   constexpr int PS = pad_shift<PADSH>();
-  if constexpr (PS > 0) return b * BS + pos * ES + (pos >> PS);
+  if constexpr (swizzled<PADSH>()) return b * BS + (pos ^ stage_swz<PL, STG>(pos >> 4)) * ES;
+  else if constexpr (PS > 0) return b * BS + pos * ES + (pos >> PS);
   else return b * BS + pos * ES;
 }
 
 // LDS read that the compiler may not pair with a neighbour into one ds_read2
 // instruction: on gfx950 a ds_read2_b64 keeps the LDS busy four times as long
 // as a ds_read_b64 (half the read bandwidth), while pairing writes costs
-// nothing.  Used where linear addressing puts reads at base + immediate.
+// nothing.  Used where linear addressing or an unpadded (swizzled) layout
+// leaves reads a multiple of 8 or 512 bytes apart from a common base.
 template <typename X> __device__ __forceinline__ X lds_rd(const X* p) {
   X v = *p;
   asm volatile("" ::: "memory");
@@ -321,7 +360,7 @@ __device__ __forceinline__ void slot_map(int tid, int i, int& b, int& j) {
 // padding period); 0 otherwise, and always 0 without linear addressing.
 template <int ES, int PADSH, int STEP> constexpr int lds_step() {
   constexpr int PS = pad_shift<PADSH>();
-  if (!linear_addr<PADSH>()) return 0;
+  if (!linear_addr<PADSH>() || swizzled<PADSH>()) return 0;
   if (PS == 0) return STEP * ES;
   if (STEP % (1 << PS) == 0) return STEP * ES + (STEP >> PS);
   return 0;
@@ -333,7 +372,7 @@ template <int ES, int PADSH, int STEP> constexpr int lds_step() {
 // slot count and the step is ES.
 template <int ES, int PADSH, int NS, int R> constexpr int lds_write_step() {
   constexpr int PS = pad_shift<PADSH>();
-  if (linear_addr<PADSH>() && NS == 1 && PS > 0 && (1 << PS) % R == 0) return ES;
+  if (linear_addr<PADSH>() && !swizzled<PADSH>() && NS == 1 && PS > 0 && (1 << PS) % R == 0) return ES;
   return lds_step<ES, PADSH, NS>();
 }
 
@@ -362,12 +401,15 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
     slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
     if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
       if constexpr (RSTEP > 0) {
-        const int a0 = lds_at<ES, BS, PADSH>(b, j);
+        const int a0 = lds_at<ES, BS, PADSH, PL, P>(b, j);
 #pragma unroll
         for (int r = 0; r < R; ++r) v[i][r] = lds_rd(&buf[a0 + r * RSTEP]);
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
+        for (int r = 0; r < R; ++r) {
+          const cx<T>* src = &buf[lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)];
+          v[i][r] = swizzled<PADSH>() ? lds_rd(src) : *src;
+        }
       }
       if constexpr (NS > 1) {
         cx<T> t[R];
@@ -392,12 +434,12 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
       const int k = j % NS;
       const int d = (j / NS) * NS * R + k;
       if constexpr (WSTEP > 0) {
-        const int a0 = lds_at<ES, BS, PADSH>(b, d);
+        const int a0 = lds_at<ES, BS, PADSH, PL, P + 1>(b, d);
 #pragma unroll
         for (int r = 0; r < R; ++r) buf[a0 + r * WSTEP] = v[i][r];
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[lds_at<ES, BS, PADSH>(b, d + r * NS)] = v[i][r];
+        for (int r = 0; r < R; ++r) buf[lds_at<ES, BS, PADSH, PL, P + 1>(b, d + r * NS)] = v[i][r];
       }
     }
   }
@@ -462,7 +504,7 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int r = 8 * (g & 1) + t;
-      float2 x = ok ? buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)] : make_float2(0.f, 0.f);
+      float2 x = ok ? buf[lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)] : make_float2(0.f, 0.f);
       if constexpr (NS > 1) {
         if (r > 0) {
           const float2 tv = tw[k * r * (N / (NS * R))];
@@ -497,7 +539,7 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int q = 4 * g + t;
-        buf[lds_at<ES, BS, PADSH>(b, d + q * NS)] = make_float2(yr[s][t], yi[s][t]);
+        buf[lds_at<ES, BS, PADSH, PL, P + 1>(b, d + q * NS)] = make_float2(yr[s][t], yi[s][t]);
       }
     }
   }
@@ -536,7 +578,7 @@ __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const floa
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       const int r = 8 * (g & 1) + t;
-      float2 x = ok ? buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)] : make_float2(0.f, 0.f);
+      float2 x = ok ? buf[lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)] : make_float2(0.f, 0.f);
       if (r > 0) {
         const float2 tv = tw[j * r];  // k = j in the last pass
         x = (S < 0) ? cmul(x, tv) : cmulc(x, tv);
@@ -611,11 +653,12 @@ __device__ __forceinline__ void fft_last_valu(cx<T>* buf, const cx<T>* tw, int t
     slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
     if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
       cx<T> v[R], t[R];
-      const int a0 = lds_at<ES, BS, PADSH>(b, j);
+      const int a0 = lds_at<ES, BS, PADSH, PL, P>(b, j);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (RSTEP > 0) v[r] = lds_rd(&buf[a0 + r * RSTEP]);
-        else v[r] = buf[lds_at<ES, BS, PADSH>(b, j + r * NBF)];
+        else if constexpr (swizzled<PADSH>()) v[r] = lds_rd(&buf[lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)]);
+        else v[r] = buf[lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)];
       }
       if constexpr (TWS) {
 #pragma unroll
@@ -629,7 +672,7 @@ __device__ __forceinline__ void fft_last_valu(cx<T>* buf, const cx<T>* tw, int t
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if ((GAP >> r) & 1u) continue;
-        if constexpr (INPLACE) buf[RSTEP > 0 ? a0 + r * RSTEP : lds_at<ES, BS, PADSH>(b, j + r * NBF)] = v[r];
+        if constexpr (INPLACE) buf[RSTEP > 0 ? a0 + r * RSTEP : lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)] = v[r];
         else store(i, r, b, j + r * NBF, v[r]);
       }
     }
@@ -660,7 +703,7 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, in
       float2* fb = reinterpret_cast<float2*>(buf);
       fft_pass_mfma_last<PL, NB, NT, ES, BS, S, P, MAP, PADSH>(
           fb, reinterpret_cast<const float2*>(tw), tid, b_act,
-          [&](int, int, int b, int pos, float2 v) { fb[lds_at<ES, BS, PADSH>(b, pos)] = v; });
+          [&](int, int, int b, int pos, float2 v) { fb[lds_at<ES, BS, PADSH, PL, P>(b, pos)] = v; });
       __syncthreads();
     } else if constexpr (P == PL::np - 1 && P > 0) {
       fft_last_valu<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, true>(buf, tw, tid, b_act,
@@ -747,10 +790,10 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
         for (int r = 0; r < FP::R; ++r) store(i, r, b, r, v[i][r]);
       } else {
         constexpr int WSTEP = lds_write_step<ES, PADSH, 1, FP::R>();
-        const int a0 = lds_at<ES, BS, PADSH>(b, j * FP::R);
+        const int a0 = lds_at<ES, BS, PADSH, PL, 1>(b, j * FP::R);
 #pragma unroll
         for (int r = 0; r < FP::R; ++r)
-          buf[WSTEP > 0 ? a0 + r * WSTEP : lds_at<ES, BS, PADSH>(b, j * FP::R + r)] = v[i][r];
+          buf[WSTEP > 0 ? a0 + r * WSTEP : lds_at<ES, BS, PADSH, PL, 1>(b, j * FP::R + r)] = v[i][r];
       }
     }
   }

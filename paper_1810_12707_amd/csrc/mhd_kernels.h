@@ -482,17 +482,25 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   constexpr int K = Band<N>::K, NHP = Band<N>::NHP;
   constexpr int NH = Band<N>::NH;
   constexpr int NB = RowShape<MODE>::NB;
-  constexpr int PADSH = 3;                    // one LDS padding slot per 8 elements
-  constexpr int BS = N + (N >> PADSH) + 1;   // padded row pitch in LDS
-  // Linear LDS addressing where the precomputed addresses would push a pass
-  // past 256 registers into spills (the flux pass from N = 512 mixed and
-  // N = 1024 FP32, the diagnostics pass at N = 1024); elsewhere they fit and
-  // were measured a little faster.
+  // LDS row layout, chosen per pass by measurement.  Linear addressing where
+  // the precomputed addresses would push a pass past 256 registers into
+  // spills (the flux pass from N = 512 mixed and N = 1024 FP32, the
+  // diagnostics pass at N = 1024).  The stage swizzle (conflict-free LDS
+  // access, but more address arithmetic) where it measured faster: the FP32
+  // flux pass below N = 512 (3%) and the FP32 velocity pass from N = 512 (2%);
+  // it made the mixed passes slower.  Otherwise one padding slot per 8
+  // elements.
   constexpr bool LIN = (MODE == RM_XB && N >= (MX ? 512 : 1024)) || (MODE == RM_XDIAG && N >= 1024);
-  constexpr int LAY = PADSH | (LIN ? kLinear : 0);
+  constexpr bool SWZ = !MX && !LIN && N % 16 == 0 && N >= 128 &&
+                       ((MODE == RM_XB && N < 512) || (MODE == RM_XA && N >= 512));
+  constexpr int PADSH = 3;
+  constexpr int LAY = SWZ ? kSwizzle : (PADSH | (LIN ? kLinear : 0));
+  // row pitch in LDS: swizzled rows are shifted by 16 elements from row to
+  // row, so that a 32-lane read spanning two rows of N = 128 uses all banks
+  constexpr int BS = SWZ ? N + 16 : N + (N >> PADSH) + 1;
   constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
   using FP = FirstPass<PL, NB, NT>;
-  auto at = [](int b, int pos) { return lds_at<1, BS, LAY>(b, pos); };
+  auto at = [](int b, int pos) { return lds_at<1, BS, LAY, PL, 0>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;

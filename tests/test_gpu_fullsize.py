@@ -154,7 +154,9 @@ def low_mode_coefficients(R, kmax):
 
 
 @pytest.mark.parametrize("n,prec", [(256, "fp32"), (512, "fp32"), (256, "fp64"), (512, "fp64"), (256, "mixed"),
-                                    (512, "mixed"), (1024, "fp32"), (1024, "mixed")])
+                                    (512, "mixed"), (1024, "fp32"), (1024, "mixed"),
+                                    # radix-3 plans (8,8,3), (8,4,4,3), (8,8,4,3) under both row layouts
+                                    (192, "fp32"), (384, "fp32"), (768, "fp32")])
 def test_rhs_exact_lowmode_state(n, prec):
     """FP64: pointwise at sampled grid points.  FP32: the rounding of P ~ 2 to
     FP32 is white noise over every mode up to K, and the divergence multiplies
