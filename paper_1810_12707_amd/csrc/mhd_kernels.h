@@ -307,14 +307,53 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
   T* const rprev = member_ptr(a.rprev, mem, ms);
   T* const rout = a.rout ? member_ptr(a.rout, mem, ms) : nullptr;
 
+  // Output (i, r) of this thread's last-pass slots: compact index, or -1 for
+  // a slot that is idle, a padding column or a dealiased kz.
+  auto out_index = [&](int i, int r, int& kx, int& ky, int& kz) -> int64_t {
+    int c, q;
+    if (!last_slot<PL, C, NT, 0>(tid, i, r, c, q)) return -1;
+    const int col = c0 + c;
+    kx = col - (col / NHP) * NHP;
+    if (col >= NCOLS || kx >= NH) return -1;
+    ky = band_k<N>(col / NHP);
+    const int l = pos_band<N>(q);
+    if (l < 0) return -1;
+    kz = band_k<N>(l);
+    return f * sc + (int64_t)l * LS + col;
+  };
+  // The state (for the update, and B^ for the resistive term) and the
+  // previous RHS: on the wide shapes from N = 512 (mixed: from 256) they are
+  // loaded before the transforms, so that these loads are in flight while the
+  // flux groups are transformed (5% and 14% faster).  At N = 256 FP32 the
+  // extra registers cost a resident workgroup and it was 4% slower, so
+  // there, and on the narrow shapes, they are loaded last.
+  constexpr bool PRE = rhs_wide<T, N, MX>() && (MX || N >= 512);
+  const bool need_state = !rout || (f >= 4 && f <= 6);
+  const bool need_prev = !rout && use_prev;
+  cx<T> u_pre[LP::CNT][LP::R], r_pre[LP::CNT][LP::R];
+  auto load_old = [&](int i, int r) {
+    u_pre[i][r] = mk<T>(0, 0);
+    r_pre[i][r] = mk<T>(0, 0);
+    int kx, ky, kz;
+    const int64_t idx = out_index(i, r, kx, ky, kz);
+    if (idx < 0) return;
+    if (need_state) u_pre[i][r] = ld(state, idx);
+    if (need_prev) r_pre[i][r] = ld(rprev, idx);
+  };
+  if constexpr (PRE) {
+#pragma unroll
+    for (int i = 0; i < LP::CNT; ++i)
+#pragma unroll
+      for (int r = 0; r < LP::R; ++r) load_old(i, r);
+  }
+
   // R_f -> store, or the AB2 update U += dt (a_cur R^n + a_prev R^{n-1}), R^{n-1} <- R^n
-  auto finish = [&](int64_t idx, cx<T> R) {
+  auto finish = [&](int64_t idx, cx<T> R, cx<T> u, cx<T> rp) {
     if (rout) {
       st(rout, idx, R);
     } else {
-      cx<T> u = ld(state, idx);
       cx<T> inc = cscale(R, ac);
-      if (use_prev) inc = cadd(inc, cscale(ld(rprev, idx), ap));
+      if (use_prev) inc = cadd(inc, cscale(rp, ap));
       u.x += dt * inc.x;
       u.y += dt * inc.y;
       st(state, idx, u);
@@ -381,25 +420,19 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
   for (int i = 0; i < LP::CNT; ++i) {
 #pragma unroll
     for (int r = 0; r < LP::R; ++r) {
-      int c, q;
-      if (!last_slot<PL, C, NT, 0>(tid, i, r, c, q)) continue;
-      const int col = c0 + c;
-      const int kx = col - (col / NHP) * NHP;
-      if (col >= NCOLS || kx >= NH) continue;
-      const int ky = band_k<N>(col / NHP);
-      const int l = pos_band<N>(q);
-      if (l < 0) continue;
-      const int64_t idx = f * sc + (int64_t)l * LS + col;
+      int kx, ky, kz;
+      const int64_t idx = out_index(i, r, kx, ky, kz);
+      if (idx < 0) continue;
+      if constexpr (!PRE) load_old(i, r);
       cx<T> R = acc[i][r];
       if (f >= 4 && f <= 6) {
         // MHD4 resistive term: - eta |k|^2 B^
-        const int kz = band_k<N>(l);
         const T k2 = T(kx * kx + ky * ky + kz * kz);
-        const cx<T> b = ld(state, idx);
+        const cx<T> b = u_pre[i][r];
         R.x -= eta * k2 * b.x;
         R.y -= eta * k2 * b.y;
       }
-      finish(idx, R);
+      finish(idx, R, u_pre[i][r], r_pre[i][r]);
     }
   }
 }
