@@ -225,6 +225,44 @@ __device__ __forceinline__ void lane_map(int w, int& b, int& j) {
   }
 }
 
+// Row maps that keep each sequence inside one wave.  MAP 3: with W = NT / 64
+// waves, sequence b belongs to wave b mod W, which walks its sequences
+// b = wave + W f (f = 0, 1, ...) butterfly-fastest, 64 lanes per slot.  Every
+// pass then reads and writes only the wave's own sequences, so passes are
+// separated by a wave-level fence instead of a workgroup barrier (LDS
+// operations of one wave are performed in order).  MAP 4 is MAP 3 with the
+// paired first-pass slots of MAP 2.
+template <int MAP> constexpr bool wave_map() { return MAP == 3 || MAP == 4; }
+template <int NB, int NT> constexpr int seqs_per_wave() { return (NB + NT / 64 - 1) / (NT / 64); }
+
+// Slots per thread of a pass over NB sequences of NBF butterflies.
+template <int NB, int NBF, int NT, int MAP> constexpr int slot_count() {
+  return wave_map<MAP>() ? (seqs_per_wave<NB, NT>() * NBF + 63) / 64 : (NB * NBF + NT - 1) / NT;
+}
+
+// Barrier between two passes: a workgroup barrier, or for the wave maps a
+// fence that keeps the compiler from moving LDS accesses across it.
+template <int MAP> __device__ __forceinline__ void pass_sync() {
+  if constexpr (wave_map<MAP>()) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// (sequence b, butterfly j) of slot i under a wave map; b >= NB when the slot
+// is idle.
+template <int NB, int NBF, int NT>
+__device__ __forceinline__ void wave_slot(int tid, int i, int& b, int& j) {
+  constexpr int W = NT / 64;
+  const int u = i * 64 + (tid & 63);
+  const int fl = u / NBF;
+  j = u - fl * NBF;
+  b = fl < seqs_per_wave<NB, NT>() ? fl * W + (tid >> 6) : NB;
+}
+
 // Butterfly (sequence b, index j) of first-pass slot i of thread tid, for NB
 // sequences of NBF butterflies spread over NT threads; false if the slot is
 // idle.  MAP 0 and 1 as lane_map on w = tid + i NT.  MAP 2 puts butterflies j
@@ -234,7 +272,20 @@ __device__ __forceinline__ void lane_map(int w, int& b, int& j) {
 template <int NB, int NBF, int NT, int MAP>
 __device__ __forceinline__ bool first_slot(int tid, int i, int& b, int& j) {
   constexpr int TOT = NB * NBF;
-  if constexpr (MAP == 2) {
+  if constexpr (MAP == 4) {
+    constexpr int CNT = slot_count<NB, NBF, NT, 4>();
+    static_assert(CNT % 2 == 0 && NBF % 2 == 0, "paired slots need an even slot count");
+    constexpr int H = CNT / 2, HB = NBF / 2;
+    const int u = (tid & 63) + (i % H) * 64;
+    const int fl = u / HB;
+    const int p = u - fl * HB;
+    j = i < H ? p : (p == 0 ? HB : NBF - p);
+    b = fl * (NT / 64) + (tid >> 6);
+    return fl < seqs_per_wave<NB, NT>() && b < NB;
+  } else if constexpr (MAP == 3) {
+    wave_slot<NB, NBF, NT>(tid, i, b, j);
+    return b < NB;
+  } else if constexpr (MAP == 2) {
     constexpr int CNT = (TOT + NT - 1) / NT;
     static_assert(CNT % 2 == 0 && NBF % 2 == 0, "paired slots need an even slot count");
     constexpr int H = CNT / 2, HB = NBF / 2;
@@ -321,6 +372,7 @@ template <typename X> __device__ __forceinline__ X lds_rd(const X* p) {
 // butterflies): MAP 1 gives j = w mod NBF and NS divides NBF, MAP 0 gives
 // j = w / NB.  The thread then reads its R - 1 twiddles once per pass.
 template <int MAP, int NB, int NBF, int NT, int NS> constexpr bool slot_invariant_k() {
+  if (MAP == 3 || MAP == 4) return 64 % NS == 0 && NBF % NS == 0;
   if (MAP == 1) return NT % NS == 0;
   if (MAP == 0) return NT % NB == 0 && (NT / NB) % NS == 0;
   return false;
@@ -344,7 +396,9 @@ __device__ __forceinline__ void load_pass_twiddles(cx<T> (&t)[R], const cx<T>* t
 // and its reads stay single ds_read_b64s.
 template <int NB, int NBF, int NT, int MAP, bool LIN = true>
 __device__ __forceinline__ void slot_map(int tid, int i, int& b, int& j) {
-  if constexpr (LIN && MAP == 1 && NT % NBF == 0) {
+  if constexpr (wave_map<MAP>()) {
+    wave_slot<NB, NBF, NT>(tid, i, b, j);
+  } else if constexpr (LIN && MAP == 1 && NT % NBF == 0) {
     b = tid / NBF + i * (NT / NBF);
     j = tid % NBF;
   } else if constexpr (LIN && MAP == 0 && NT % NB == 0) {
@@ -384,7 +438,7 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
   constexpr int NS = plan_ns<PL>(P);
   constexpr int NBF = N / R;
   constexpr int TOT = NB * NBF;
-  constexpr int CNT = (TOT + NT - 1) / NT;
+  constexpr int CNT = slot_count<NB, NBF, NT, MAP>();
   constexpr bool TWS = NS > 1 && CNT > 1 && slot_invariant_k<MAP, NB, NBF, NT, NS>();
   constexpr int RSTEP = lds_step<ES, PADSH, NBF>();
   constexpr int WSTEP = lds_write_step<ES, PADSH, NS, R>();
@@ -399,7 +453,7 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
   for (int i = 0; i < CNT; ++i) {
     int b, j;
     slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
-    if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
+    if ((wave_map<MAP>() || TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
       if constexpr (RSTEP > 0) {
         const int a0 = lds_at<ES, BS, PADSH, PL, P>(b, j);
 #pragma unroll
@@ -425,12 +479,12 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
       dft<R, S>(v[i]);
     }
   }
-  __syncthreads();
+  pass_sync<MAP>();
 #pragma unroll
   for (int i = 0; i < CNT; ++i) {
     int b, j;
     slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
-    if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
+    if ((wave_map<MAP>() || TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
       const int k = j % NS;
       const int d = (j / NS) * NS * R + k;
       if constexpr (WSTEP > 0) {
@@ -443,7 +497,7 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
       }
     }
   }
-  __syncthreads();
+  pass_sync<MAP>();
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -479,6 +533,7 @@ __device__ __forceinline__ void dft16_operands(int lane, bf16x8& a0h, bf16x8& a0
 // the products lane (n, g) holds outputs q = 4g .. 4g+3 of butterfly n.
 template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH>
 __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int tid, int b_act) {
+  static_assert(!wave_map<MAP>(), "MFMA passes use the workgroup lane maps");
   constexpr int N = PL::N;
   constexpr int R = 16;
   constexpr int NS = plan_ns<PL>(P);
@@ -555,6 +610,7 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
 template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH, class Store, bool SLOTS = false>
 __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const float2* tw, int tid, int b_act,
                                                    Store&& store) {
+  static_assert(!wave_map<MAP>(), "MFMA passes use the workgroup lane maps");
   constexpr int N = PL::N;
   constexpr int R = 16;
   constexpr int NS = plan_ns<PL>(P);
@@ -637,7 +693,7 @@ __device__ __forceinline__ void fft_last_valu(cx<T>* buf, const cx<T>* tw, int t
   constexpr int R = PL::r[P];
   constexpr int NBF = N / R;
   constexpr int TOT = NB * NBF;
-  constexpr int CNT = (TOT + NT - 1) / NT;
+  constexpr int CNT = slot_count<NB, NBF, NT, MAP>();
   constexpr unsigned GAP = gap_rows<N, NBF, R, KEEP>();
   constexpr bool TWS = CNT > 1 && slot_invariant_k<MAP, NB, NBF, NT, NBF>();
   constexpr int RSTEP = lds_step<ES, PADSH, NBF>();
@@ -651,7 +707,7 @@ __device__ __forceinline__ void fft_last_valu(cx<T>* buf, const cx<T>* tw, int t
   for (int i = 0; i < CNT; ++i) {
     int b, j;
     slot_map<NB, NBF, NT, MAP, linear_addr<PADSH>()>(tid, i, b, j);
-    if ((TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
+    if ((wave_map<MAP>() || TOT % NT == 0 || tid + i * NT < TOT) && b < b_act) {
       cx<T> v[R], t[R];
       const int a0 = lds_at<ES, BS, PADSH, PL, P>(b, j);
 #pragma unroll
@@ -704,11 +760,11 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, in
       fft_pass_mfma_last<PL, NB, NT, ES, BS, S, P, MAP, PADSH>(
           fb, reinterpret_cast<const float2*>(tw), tid, b_act,
           [&](int, int, int b, int pos, float2 v) { fb[lds_at<ES, BS, PADSH, PL, P>(b, pos)] = v; });
-      __syncthreads();
+      pass_sync<MAP>();
     } else if constexpr (P == PL::np - 1 && P > 0) {
       fft_last_valu<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, true>(buf, tw, tid, b_act,
                                                                        [](int, int, int, int, cx<T>) {});
-      __syncthreads();
+      pass_sync<MAP>();
     } else {
       fft_pass<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
       lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, P + 1>(buf, tw, tid, b_act);
@@ -727,11 +783,11 @@ __device__ __forceinline__ void fft_mid_passes(cx<T>* buf, const cx<T>* tw, int 
 
 // Shape of the first pass of a plan: R elements per butterfly, CNT
 // butterflies per thread.
-template <class PL, int NB, int NT> struct FirstPass {
+template <class PL, int NB, int NT, int MAP = 1> struct FirstPass {
   static constexpr int R = PL::r[0];
   static constexpr int NBF = PL::N / R;
   static constexpr int TOT = NB * NBF;
-  static constexpr int CNT = (TOT + NT - 1) / NT;
+  static constexpr int CNT = slot_count<NB, NBF, NT, MAP>();
 };
 
 // Per-thread shape of the last pass: outputs are handed to store(i, r, ...)
@@ -776,9 +832,9 @@ __device__ __forceinline__ bool last_slot(int tid, int i, int r, int& b, int& po
 // final outputs (one-pass plans) or the LDS writes of the next pass, followed
 // by a barrier.
 template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
-__device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<PL, NB, NT>::CNT][PL::r[0]],
+__device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<PL, NB, NT, MAP>::CNT][PL::r[0]],
                                                int tid, int b_act, Store&& store) {
-  using FP = FirstPass<PL, NB, NT>;
+  using FP = FirstPass<PL, NB, NT, MAP>;
   constexpr int NP = PL::np;
 #pragma unroll
   for (int i = 0; i < FP::CNT; ++i) {
@@ -797,7 +853,7 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
       }
     }
   }
-  if constexpr (NP > 1) __syncthreads();
+  if constexpr (NP > 1) pass_sync<MAP>();
 }
 
 // Middle passes (LDS to LDS) and the last pass, whose outputs go to
@@ -842,7 +898,7 @@ template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP =
 __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Load&& load,
                                         Store&& store) {
   static_assert(plan_ok<PL>(), "radix plan does not multiply to N");
-  using FP = FirstPass<PL, NB, NT>;
+  using FP = FirstPass<PL, NB, NT, MAP>;
   cx<T> v[FP::CNT][FP::R];
 #pragma unroll
   for (int i = 0; i < FP::CNT; ++i) {

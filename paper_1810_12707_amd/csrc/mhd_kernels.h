@@ -322,12 +322,12 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
     return f * sc + (int64_t)l * LS + col;
   };
   // The state (for the update, and B^ for the resistive term) and the
-  // previous RHS: on the wide shapes from N = 512 (mixed: from 256) they are
-  // loaded before the transforms, so that these loads are in flight while the
-  // flux groups are transformed (5% and 14% faster).  At N = 256 FP32 the
-  // extra registers cost a resident workgroup and it was 4% slower, so
-  // there, and on the narrow shapes, they are loaded last.
-  constexpr bool PRE = rhs_wide<T, N, MX>() && (MX || N >= 512);
+  // previous RHS: on the wide shapes -- FP32 from N = 512, mixed at 256 and
+  // 512 -- they are loaded before the transforms, so that these loads are in
+  // flight while the flux groups are transformed (5% and 14% faster).  FP32
+  // at N = 256 (a resident workgroup lost to registers, 4% slower) and mixed
+  // at 1024 (18% slower) load them last, as do the narrow shapes.
+  constexpr bool PRE = rhs_wide<T, N, MX>() && (MX ? N <= 512 : N >= 512);
   const bool need_state = !rout || (f >= 4 && f <= 6);
   const bool need_prev = !rout && use_prev;
   cx<T> u_pre[LP::CNT][LP::R], r_pre[LP::CNT][LP::R];
@@ -532,7 +532,16 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   // row, so that a 32-lane read spanning two rows of N = 128 uses all banks
   constexpr int BS = SWZ ? N + 16 : N + (N >> PADSH) + 1;
   constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
-  using FP = FirstPass<PL, NB, NT>;
+  // From N = 512 the velocity and flux passes (VALU plans) keep each field's
+  // transforms inside one wave (wave maps): between their passes a wave-level
+  // fence replaces the workgroup barrier, and only the pointwise stage, which
+  // reads every field at one point, is bracketed by barriers (12% and 5%
+  // faster at N = 512).  Not at N = 256, where half-wide passes would leave
+  // lanes idle in every wave and the flux pass would lose a resident
+  // workgroup to registers, nor with fewer fields than waves.
+  constexpr bool WAVE = !MX && (MODE == RM_XA || MODE == RM_XB) && N >= 512 && NB >= NT / 64;
+  constexpr int RMAP = WAVE ? 3 : 1;
+  using FP = FirstPass<PL, NB, NT, RMAP>;
   auto at = [](int b, int pos) { return lds_at<1, BS, LAY, PL, 0>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
@@ -557,6 +566,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   constexpr int RH = FP::R / 2;
   constexpr int FMAP = (FP::CNT % 2 == 0 && FP::NBF % 2 == 0) ? 2 : ((FP::NBF >= 2 && 64 % FP::NBF == 0) ? 3 : 1);
   constexpr int HC = FP::CNT / 2;
+  constexpr int FM1 = FMAP == 2 ? (WAVE ? 4 : 2) : RMAP;  // lane map of the first pass
   cx<T> p0[FP::CNT][RH], p1[FP::CNT][RH];
   auto issue = [&](int64_t item) {
     const int mi = (int)(item / rows_per_mem);
@@ -565,7 +575,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
 #pragma unroll
     for (int i = 0; i < FP::CNT; ++i) {
       int b, j;
-      const bool ok = first_slot<NB, FP::NBF, NT, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
+      const bool ok = first_slot<NB, FP::NBF, NT, FM1>(tid, i, b, j) && b < nin;
       const T* src = in0 + 2 * b * a.in_stride;
 #pragma unroll
       for (int r = 0; r < RH; ++r) {
@@ -604,7 +614,10 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
         cur_m = mem;
       }
     }
-    __syncthreads();  // the previous row pair is done with the LDS
+    // the previous row pair is done with the LDS (with wave maps a wave only
+    // writes its own fields before the next barrier, and it is the only one
+    // that still reads them)
+    if constexpr (!WAVE) __syncthreads();
     if constexpr (!SPEC_IN) {
       // real rows -> packed complex row0 + i row1
       for (int e = tid; e < nin * N; e += NT) {
@@ -628,7 +641,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
 #pragma unroll
       for (int i = 0; i < FP::CNT; ++i) {
         int b, j;
-        const bool ok = first_slot<NB, FP::NBF, NT, (FMAP == 2 ? 2 : 1)>(tid, i, b, j) && b < nin;
+        const bool ok = first_slot<NB, FP::NBF, NT, FM1>(tid, i, b, j) && b < nin;
         const T* src = member_ptr(a.in0, mem, a.bt.mstride) + 2 * b * a.in_stride;
         // FMAP 3: lane of butterfly NBF - j (j = tid mod NBF since NBF divides 64)
         const int plane = (tid & 63) - j + (FP::NBF - j) % FP::NBF;
@@ -686,9 +699,9 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           v[i][r] = z;
         }
       }
-      fft_first_regs<T, PL, NB, NT, 1, BS, +1, (FMAP == 2 ? 2 : 1), LAY>(buf, v, tid, nin, lds_store);
+      fft_first_regs<T, PL, NB, NT, 1, BS, +1, FM1, LAY>(buf, v, tid, nin, lds_store);
       if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
-      fft_rest<T, PL, NB, NT, 1, BS, +1, 1, LAY, false, true>(buf, stw, tid, nin, lds_store);
+      fft_rest<T, PL, NB, NT, 1, BS, +1, RMAP, LAY, false, true>(buf, stw, tid, nin, lds_store);
     }
     __syncthreads();
 
@@ -822,12 +835,11 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
 
     if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
       __syncthreads();
-      lds_fft<T, PL, NB, NT, 1, BS, -1, 1, LAY, K>(buf, stw, tid, nout);  // only k <= K and N - k are read
+      lds_fft<T, PL, NB, NT, 1, BS, -1, RMAP, LAY, K>(buf, stw, tid, nout);  // only k <= K and N - k are read
       // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
       T* out0 = member_ptr(a.out0, mem, a.bt.mstride);
       const int64_t ost = a.out_stride;
-      for (int e = tid; e < nout * NH; e += NT) {
-        const int fld = e / NH, k = e - (e / NH) * NH;
+      auto unpack = [&](int fld, int k) {
         const cx<T> zk = buf[at(fld, k)];
         const cx<T> zm = buf[at(fld, k == 0 ? 0 : N - k)];
         const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
@@ -835,6 +847,18 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
         T* dst = out0 + 2 * fld * ost;
         st(dst, row0 * NHP + k, x0);
         st(dst, (row0 + 1) * NHP + k, x1);
+      };
+      if constexpr (WAVE) {
+        // each wave unpacks the fields it transformed
+        constexpr int W = NT / 64;
+        const int wv = tid >> 6;
+        for (int e = tid & 63; e < seqs_per_wave<NB, NT>() * NH; e += 64) {
+          const int fl = e / NH;
+          const int fld = fl * W + wv;
+          if (fld < nout) unpack(fld, e - fl * NH);
+        }
+      } else {
+        for (int e = tid; e < nout * NH; e += NT) unpack(e / NH, e - (e / NH) * NH);
       }
     }
   }
