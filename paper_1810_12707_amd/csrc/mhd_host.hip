@@ -35,53 +35,59 @@ Registry& registry() {
 
 // ------------------------------------------------------------------ reductions
 
-// Block q reduces column q of part[nrec][nq]: thread t takes records t, t+256,
-// ... with a Neumaier sum (or a NaN-propagating max when bit q of max_mask is
-// set); thread 0 then combines the 256 partials in thread order.  The result
-// is written to out[q], or merged as max(out[q], result) when merge_max.
+// One launch for both record sets of the diagnostics.  Block q reduces
+// column q of p1[n1][nq1] into out1[q] for q < nq1, else column q - nq1 of
+// p2[n2][nq2] into out2[q - nq1].  Thread t takes records t, t + 256, ... with
+// a Neumaier sum (or a NaN-propagating max when bit q of max_mask is set; the
+// mask applies to the first set), and the 256 (sum, compensation) pairs are
+// combined pairwise in a fixed tree.  Deterministic for given record counts.
+__device__ __forceinline__ void two_sum_into(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
 __global__ void __launch_bounds__(kThreads)
-k_reduce(const double* __restrict__ part, int64_t nrec, int nq, unsigned max_mask, int merge_max,
-         double* __restrict__ out) {
+k_reduce(const double* __restrict__ p1, int64_t n1, int nq1, unsigned max_mask, const double* __restrict__ p2,
+         int64_t n2, int nq2, double* __restrict__ out1, double* __restrict__ out2) {
   __shared__ double s_s[kThreads];
   __shared__ double s_c[kThreads];
-  const int q = blockIdx.x;
+  const bool first = (int)blockIdx.x < nq1;
+  const int q = first ? (int)blockIdx.x : (int)blockIdx.x - nq1;
+  const double* part = first ? p1 : p2;
+  const int64_t nrec = first ? n1 : n2;
+  const int nq = first ? nq1 : nq2;
   const int tid = threadIdx.x;
-  const bool is_max = (max_mask >> q) & 1u;
+  const bool is_max = first && ((max_mask >> q) & 1u);
   double s = 0.0, c = 0.0;
   for (int64_t r = tid; r < nrec; r += kThreads) {
     const double x = part[r * nq + q];
     if (is_max) {
       if (!(x <= s)) s = x;
     } else {
-      const double t = s + x;
-      if (fabs(s) >= fabs(x)) c += (s - t) + x;
-      else c += (x - t) + s;
-      s = t;
+      two_sum_into(s, c, x);
     }
   }
   s_s[tid] = s;
   s_c[tid] = c;
   __syncthreads();
-  if (tid == 0) {
-    double S = 0.0, Cc = 0.0;
-    for (int i = 0; i < kThreads; ++i) {
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
       if (is_max) {
-        if (!(s_s[i] <= S)) S = s_s[i];
+        if (!(s_s[tid + w] <= s_s[tid])) s_s[tid] = s_s[tid + w];
       } else {
-        const double x = s_s[i];
-        const double t = S + x;
-        if (fabs(S) >= fabs(x)) Cc += (S - t) + x;
-        else Cc += (x - t) + S;
-        S = t;
-        Cc += s_c[i];
+        double a = s_s[tid], ca = s_c[tid] + s_c[tid + w];
+        two_sum_into(a, ca, s_s[tid + w]);
+        s_s[tid] = a;
+        s_c[tid] = ca;
       }
     }
-    const double r = is_max ? S : S + Cc;
-    if (merge_max) {
-      if (!(r <= out[q])) out[q] = r;
-    } else {
-      out[q] = r;
-    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double r = is_max ? s_s[0] : s_s[0] + s_c[0];
+    (first ? out1 : out2)[q] = r;
   }
 }
 
@@ -220,7 +226,7 @@ Geo make_geo(int n) {
 }
 
 struct Layout {
-  size_t tw, state, rprev, uhat, tstate, trhs, iz, iy, part, status, res, total;
+  size_t tw, state, rprev, uhat, tstate, trhs, iz, iy, part, spart, status, res, total;
 };
 
 Layout make_layout(const Geo& g, size_t tsize) {
@@ -238,9 +244,8 @@ Layout make_layout(const Geo& g, size_t tsize) {
   L.iy = take(16 * (size_t)g.iy * cplx);
   const size_t rows = (size_t)g.n * g.n / 2;
   const size_t spec_blocks = (size_t)((g.sc + kThreads - 1) / kThreads);
-  size_t pd = rows * kDiagQ;
-  if (spec_blocks * kSpecQ > pd) pd = spec_blocks * kSpecQ;
-  L.part = take(pd * sizeof(double));
+  L.part = take(rows * kDiagQ * sizeof(double));
+  L.spart = take(spec_blocks * kSpecQ * sizeof(double));
   L.status = take(kStatusWords * sizeof(double));
   L.res = take(kResWords * sizeof(double));
   L.total = off;
@@ -351,6 +356,7 @@ struct Engine {
   T* iy(int slot) const { return at(c->L.iy) + 2 * (size_t)slot * g.iy; }
   T* spec_field(T* base, int f) const { return base + 2 * (size_t)f * g.sc; }
   double* part() const { return reinterpret_cast<double*>(c->ws + c->L.part); }
+  double* spart() const { return reinterpret_cast<double*>(c->ws + c->L.spart); }
   unsigned* status() const { return reinterpret_cast<unsigned*>(c->ws + c->L.status); }
   unsigned* scratch_status() const { return status() + 2; }
   double* res() const { return reinterpret_cast<double*>(c->ws + c->L.res); }
@@ -644,31 +650,27 @@ struct Engine {
     const T* zi[8];
     for (int f = 0; f < 8; ++f) zi[f] = spec_field(U, f);
     enum { X = 0, Y = 1, Z = 2 };
-    OutSpec sp[12];
+    constexpr int NF = kDiagFields;  // the state and div B
+    OutSpec sp[NF];
     for (int f = 0; f < 8; ++f) sp[f] = copy_spec(f, s);
-    sp[8] = spec({term(6, Y, s), term(5, Z, -s)});   // J_x
-    sp[9] = spec({term(4, Z, s), term(6, X, -s)});   // J_y
-    sp[10] = spec({term(5, X, s), term(4, Y, -s)});  // J_z
-    sp[11] = spec({term(4, X, s), term(5, Y, s), term(6, Z, s)});  // div B
-    T* zo[12];
-    for (int f = 0; f < 12; ++f) zo[f] = iz(f);
-    col(PK_ZINV, 12, zi, 8, zo, sp);
-    T* yo[12];
-    for (int f = 0; f < 12; ++f) yo[f] = iy(f);
-    y_copy(PK_YINV, 12, zo, yo);
+    sp[8] = spec({term(4, X, s), term(5, Y, s), term(6, Z, s)});  // div B
+    T* zo[NF];
+    for (int f = 0; f < NF; ++f) zo[f] = iz(f);
+    col(PK_ZINV, NF, zi, 8, zo, sp);
+    T* yo[NF];
+    for (int f = 0; f < NF; ++f) yo[f] = iy(f);
+    y_copy(PK_YINV, NF, zo, yo);
     RowArgs<T> r = row_args();
     set_in(r, 0);
     r.partials = part();
     const dim3 grid = row_grid(RM_XDIAG);  // one partial record per workgroup (<= n^2/2)
     k.row(RM_XDIAG, r, grid, c->stream);
-    const unsigned maxmask = (1u << DQ_DIVB_MAX) | (1u << DQ_CFL_MAX);
-    hipLaunchKernelGGL(k_reduce, dim3(kDiagQ), dim3(kThreads), 0, c->stream, part(), (int64_t)grid.x, kDiagQ,
-                       maxmask, 0, res());
     const int sblocks = (int)((g.sc + kThreads - 1) / kThreads);
     hipLaunchKernelGGL((k_spec_diag<T>), dim3(sblocks), dim3(kThreads), 0, c->stream, spec_field(U, 4),
-                       spec_field(U, 5), spec_field(U, 6), g, part());
-    hipLaunchKernelGGL(k_reduce, dim3(kSpecQ), dim3(kThreads), 0, c->stream, part(), (int64_t)sblocks, kSpecQ, 0u,
-                       0, res() + 16);
+                       spec_field(U, 5), spec_field(U, 6), g, spart());
+    const unsigned maxmask = (1u << DQ_DIVB_MAX) | (1u << DQ_CFL_MAX);
+    hipLaunchKernelGGL(k_reduce, dim3(kDiagQ + kSpecQ), dim3(kThreads), 0, c->stream, part(), (int64_t)grid.x,
+                       kDiagQ, maxmask, spart(), (int64_t)sblocks, kSpecQ, res(), res() + 16);
   }
 };
 

@@ -23,13 +23,14 @@ constexpr int kMaxTerms = 3;   // terms of one spectral linear combination
 constexpr int kMaxOut = 12;    // outputs of one column launch
 constexpr int kMaxIn = 12;     // inputs of one column launch
 constexpr int kRowFields = 16; // fields held by one row (x) pass
-constexpr int kDiagQ = 15;     // diagnostic partial sums per block
+constexpr int kDiagQ = 14;     // diagnostic partial sums per block
+constexpr int kDiagFields = 9;  // real-space inputs of the diagnostics pass: the state and div B
 constexpr int kSpecQ = 3;      // spectral diagnostic partial sums per block
 
 // Index of each real-space diagnostic partial.
 enum DiagQ {
   DQ_RHO = 0, DQ_MX, DQ_MY, DQ_MZ, DQ_EKIN, DQ_EMAG, DQ_P, DQ_E, DQ_HC,
-  DQ_UABS, DQ_BABS, DQ_DIVB_MAX, DQ_CFL_MAX, DQ_NONFINITE, DQ_J2
+  DQ_UABS, DQ_BABS, DQ_DIVB_MAX, DQ_CFL_MAX, DQ_NONFINITE
 };
 // Index of each spectral diagnostic partial.
 enum SpecQ { SQ_HM = 0, SQ_DIVB2, SQ_J2 };

@@ -444,7 +444,7 @@ template <> struct RowShape<RM_XA> { static constexpr int NIN = 4, NOUT = 3, NB 
 template <> struct RowShape<RM_XB> { static constexpr int NIN = 16, NOUT = 12, NB = 16; };
 template <> struct RowShape<RM_XFWD_REAL> { static constexpr int NIN = 8, NOUT = 8, NB = 8; };
 template <> struct RowShape<RM_XINV_REAL> { static constexpr int NIN = 8, NOUT = 8, NB = 8; };
-template <> struct RowShape<RM_XDIAG> { static constexpr int NIN = 12, NOUT = 0, NB = 12; };
+template <> struct RowShape<RM_XDIAG> { static constexpr int NIN = kDiagFields, NOUT = 0, NB = kDiagFields; };
 
 template <typename T>
 __device__ __forceinline__ bool finite_(T v) { return isfinite(v); }
@@ -797,14 +797,15 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     }
 
     if constexpr (MODE == RM_XDIAG) {
-      // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8-10 J, 11 div B.
+      // Inputs: 0 rho, 1-3 m, 4-6 B, 7 E, 8 div B.  (The current's mean square is
+      // a spectral sum, exact by Parseval for the band-limited B^.)
       const double gm1 = a.gamma[mem] - 1.0, gam = a.gamma[mem];
       for (int x = tid; x < N; x += NT) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           auto g = [&](int f) -> double { const cx<T> v = buf[at(f, x)]; return double(h == 0 ? v.x : v.y); };
           const double rho = g(0), mx = g(1), my = g(2), mz = g(3), Bx = g(4), By = g(5), Bz = g(6), E = g(7);
-          const double Jx = g(8), Jy = g(9), Jz = g(10), dB = g(11);
+          const double dB = g(8);
           const double ux = mx / rho, uy = my / rho, uz = mz / rho;
           const double B2 = Bx * Bx + By * By + Bz * Bz;
           const double mu = mx * ux + my * uy + mz * uz;
@@ -827,7 +828,6 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           const bool fin = isfinite(rho) && isfinite(mx) && isfinite(my) && isfinite(mz) && isfinite(Bx) &&
                            isfinite(By) && isfinite(Bz) && isfinite(E);
           q[DQ_NONFINITE] += fin ? 0.0 : 1.0;
-          q[DQ_J2] += Jx * Jx + Jy * Jy + Jz * Jz;
         }
       }
       continue;
