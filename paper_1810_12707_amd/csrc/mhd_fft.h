@@ -85,13 +85,11 @@ template <int S, typename X> __device__ __forceinline__ void dft4(X* v) {
   v[3] = csub(t1, t3);
 }
 
-template <int S, typename X> __device__ __forceinline__ void dft8(X* v) {
+// Second half of an 8-point DFT from the 4-point DFTs e of the even and o of
+// the odd samples.
+template <int S, typename X> __device__ __forceinline__ void dft8_combine(X* v, X (&e)[4], X (&o)[4]) {
   using T = decltype(v[0].x);
   const T h = T(0.70710678118654752440084436210485);
-  X e[4] = {v[0], v[2], v[4], v[6]};
-  X o[4] = {v[1], v[3], v[5], v[7]};
-  dft4<S>(e);
-  dft4<S>(o);
   // o[q] *= exp(S * i * pi * q / 4)
   X o1 = o[1], o3 = o[3];
   if (S < 0) {
@@ -107,6 +105,28 @@ template <int S, typename X> __device__ __forceinline__ void dft8(X* v) {
     v[q] = cadd(e[q], o[q]);
     v[q + 4] = csub(e[q], o[q]);
   }
+}
+
+template <int S, typename X> __device__ __forceinline__ void dft8(X* v) {
+  X e[4] = {v[0], v[2], v[4], v[6]};
+  X o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<S>(e);
+  dft4<S>(o);
+  dft8_combine<S>(v, e, o);
+}
+
+// 8-point DFT of samples with v[3] = v[4] = 0 (a first pass over a band-limited
+// input whose rows 3 and 4 fall in the dealiased gap): the 4-point DFTs lose
+// two complex additions each.  Equal to dft8 on such input up to the sign of
+// zero results.
+template <int S, typename X> __device__ __forceinline__ void dft8_z34(X* v) {
+  const X a = cadd(v[2], v[6]);
+  const X d = ctimes_si<S>(csub(v[2], v[6]));
+  X e[4] = {cadd(v[0], a), cadd(v[0], d), csub(v[0], a), csub(v[0], d)};
+  const X t0 = cadd(v[1], v[5]), t1 = csub(v[1], v[5]);
+  const X w = ctimes_si<S>(v[7]);
+  X o[4] = {cadd(t0, v[7]), csub(t1, w), csub(t0, v[7]), cadd(t1, w)};
+  dft8_combine<S>(v, e, o);
 }
 
 // 16 = 4 x 4: inner 4-point DFTs over stride-4 samples, twiddles
@@ -136,6 +156,10 @@ template <int S, typename X> __device__ __forceinline__ void dft16(X* v) {
   }
 }
 
+// DFT of samples of which those with bit r of ZM set are known to be zero
+// (only the 8-point case with samples 3 and 4 zero is specialised).
+template <int R, int S, unsigned ZM, typename X> __device__ __forceinline__ void dft_z(X* v);
+
 template <int R, int S, typename X> __device__ __forceinline__ void dft(X* v) {
   if constexpr (R == 2) dft2<S>(v);
   else if constexpr (R == 3) dft3<S>(v);
@@ -143,6 +167,11 @@ template <int R, int S, typename X> __device__ __forceinline__ void dft(X* v) {
   else if constexpr (R == 8) dft8<S>(v);
   else if constexpr (R == 16) dft16<S>(v);
   else static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "unsupported radix");
+}
+
+template <int R, int S, unsigned ZM, typename X> __device__ __forceinline__ void dft_z(X* v) {
+  if constexpr (R == 8 && ZM == ((1u << 3) | (1u << 4))) dft8_z34<S>(v);
+  else dft<R, S>(v);
 }
 
 // ---------------------------------------------------------------- radix plans
@@ -831,7 +860,8 @@ __device__ __forceinline__ bool last_slot(int tid, int i, int r, int& b, int& po
 // sequence b for this thread's i-th butterfly): R-point DFTs, then either the
 // final outputs (one-pass plans) or the LDS writes of the next pass, followed
 // by a barrier.
-template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, class Store>
+template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, unsigned ZM = 0,
+          class Store>
 __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<PL, NB, NT, MAP>::CNT][PL::r[0]],
                                                int tid, int b_act, Store&& store) {
   using FP = FirstPass<PL, NB, NT, MAP>;
@@ -840,7 +870,7 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
   for (int i = 0; i < FP::CNT; ++i) {
     int b, j;
     if (first_slot<NB, FP::NBF, NT, MAP>(tid, i, b, j) && b < b_act) {
-      dft<FP::R, S>(v[i]);
+      dft_z<FP::R, S, ZM>(v[i]);
       if constexpr (NP == 1) {
 #pragma unroll
         for (int r = 0; r < FP::R; ++r) store(i, r, b, r, v[i][r]);

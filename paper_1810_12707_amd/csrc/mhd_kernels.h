@@ -35,15 +35,19 @@ template <typename T, int N> constexpr int col_width() {
 }
 
 // Threads and tile width of the forward-z RHS pass.  It is latency-bound
-// (three dependent memory phases per workgroup: the first flux group, the
-// second, the state and history), so it wants many resident waves: FP32 at
-// N >= 256 runs 512 threads with one first-pass butterfly each (16 columns at
-// N = 256, 8 above), which keeps registers low (five or more waves per SIMD).
+// (dependent memory phases per workgroup: the first flux group, the second,
+// the state and history), so it wants many resident waves: FP32 at N >= 256
+// runs one first-pass butterfly per thread, which keeps registers low -- 512
+// threads on 16 columns at N = 256, 1024 threads on 16 columns at N = 512
+// (whole 128-byte row segments; 3% faster than 512 threads on 8), 512
+// threads on 8 columns above and for the mixed path.
 template <typename T, int N, bool MX> constexpr bool rhs_wide() { return sizeof(T) == 4 && N >= 256; }
 template <typename T, int N, bool MX> constexpr int rhs_threads() {
+  if (sizeof(T) == 4 && !MX && N == 512) return 4 * kThreads;
   return rhs_wide<T, N, MX>() ? 2 * kThreads : kThreads;
 }
 template <typename T, int N, bool MX> constexpr int rhs_tile() {
+  if (sizeof(T) == 4 && !MX && N == 512) return 16;
   return rhs_wide<T, N, MX>() ? (N == 256 ? 16 : 8) : col_width<T, N>();
 }
 // Minimum resident waves per SIMD asked of the compiler (register cap).
@@ -567,6 +571,9 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   constexpr int FMAP = (FP::CNT % 2 == 0 && FP::NBF % 2 == 0) ? 2 : ((FP::NBF >= 2 && 64 % FP::NBF == 0) ? 3 : 1);
   constexpr int HC = FP::CNT / 2;
   constexpr int FM1 = FMAP == 2 ? (WAVE ? 4 : 2) : RMAP;  // lane map of the first pass
+  // first-pass rows r whose positions j + r NBF all lie in the dealiased gap:
+  // known zeros, neither loaded nor assembled, and pruned from the DFT
+  constexpr unsigned ZROWS = gap_rows<N, FP::NBF, FP::R, K>();
   cx<T> p0[FP::CNT][RH], p1[FP::CNT][RH];
   auto issue = [&](int64_t item) {
     const int mi = (int)(item / rows_per_mem);
@@ -582,6 +589,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
         const int q = j + r * FP::NBF;
         p0[i][r] = mk<T>(0, 0);  // the previous pair's values are dead
         p1[i][r] = mk<T>(0, 0);
+        if ((ZROWS >> r) & 1u) continue;
         if (ok && q <= K) {
           p0[i][r] = ld(src, row0 * NHP + q);
           p1[i][r] = ld(src, (row0 + 1) * NHP + q);
@@ -647,6 +655,10 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
         const int plane = (tid & 63) - j + (FP::NBF - j) % FP::NBF;
 #pragma unroll
         for (int r = 0; r < FP::R; ++r) {
+          if ((ZROWS >> r) & 1u) {
+            v[i][r] = mk<T>(0, 0);
+            continue;
+          }
           const int q = j + r * FP::NBF;
           cx<T> x0 = mk<T>(0, 0), x1 = mk<T>(0, 0);
           if (r < RH) {
@@ -699,7 +711,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           v[i][r] = z;
         }
       }
-      fft_first_regs<T, PL, NB, NT, 1, BS, +1, FM1, LAY>(buf, v, tid, nin, lds_store);
+      fft_first_regs<T, PL, NB, NT, 1, BS, +1, FM1, LAY, ZROWS>(buf, v, tid, nin, lds_store);
       if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
       fft_rest<T, PL, NB, NT, 1, BS, +1, RMAP, LAY, false, true>(buf, stw, tid, nin, lds_store);
     }
