@@ -636,7 +636,8 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
 // multiplied and handed to store(s, t, b, pos, value) (s = group slot of this
 // wave, t = 0..3 the lane's four outputs) before the next group is read.
 // store() may write the LDS positions in place.
-template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH, class Store, bool SLOTS = false>
+template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH, class Store, bool SLOTS = false,
+          int UNR = 1>
 __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const float2* tw, int tid, int b_act,
                                                    Store&& store) {
   static_assert(!wave_map<MAP>(), "MFMA passes use the workgroup lane maps");
@@ -685,11 +686,19 @@ __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const floa
       for (int t = 0; t < 4; ++t) store(s, t, b, j + (4 * g + t) * NS, make_float2(c0[t], c1[t]));
     }
   };
-  // The groups run one after another.  The loop is unrolled only when the
-  // store keeps its results in registers indexed by the group slot; rolled,
-  // the compiler cannot hoist every group's loads and hold them all.
+  // The groups run one after another.  The loop is unrolled completely when
+  // the store keeps its results in registers indexed by the group slot;
+  // otherwise by UNR groups (1, 2 or 4, per kernel by measurement), which
+  // overlaps one group's LDS latency and MFMA chain with the next group's
+  // work at the cost of registers.
   if constexpr (SLOTS) {
 #pragma unroll
+    for (int s = 0; s < GPW; ++s) group(s);
+  } else if constexpr (UNR >= 4) {
+#pragma unroll 4
+    for (int s = 0; s < GPW; ++s) group(s);
+  } else if constexpr (UNR == 2) {
+#pragma unroll 2
     for (int s = 0; s < GPW; ++s) group(s);
   } else {
 #pragma unroll 1
@@ -780,15 +789,15 @@ __device__ __forceinline__ void fft_pass(cx<T>* buf, const cx<T>* tw, int tid, i
 // KEEP > 0: only positions <= KEEP and >= N - KEEP of the result are wanted
 // (the others may be left stale).
 template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP = 0, int PADSH = 0, int KEEP = 0,
-          int P = 0>
+          int UNR = 1, int P = 0>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, int b_act) {
   static_assert(plan_ok<PL>(), "radix plan does not multiply to N");
   if constexpr (P < PL::np) {
     if constexpr (PL::MX && PL::r[P] == 16 && P == PL::np - 1 && P > 0) {
       float2* fb = reinterpret_cast<float2*>(buf);
-      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, P, MAP, PADSH>(
-          fb, reinterpret_cast<const float2*>(tw), tid, b_act,
-          [&](int, int, int b, int pos, float2 v) { fb[lds_at<ES, BS, PADSH, PL, P>(b, pos)] = v; });
+      auto st = [&](int, int, int b, int pos, float2 v) { fb[lds_at<ES, BS, PADSH, PL, P>(b, pos)] = v; };
+      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, P, MAP, PADSH, decltype(st)&, false, UNR>(
+          fb, reinterpret_cast<const float2*>(tw), tid, b_act, st);
       pass_sync<MAP>();
     } else if constexpr (P == PL::np - 1 && P > 0) {
       fft_last_valu<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, true>(buf, tw, tid, b_act,
@@ -796,7 +805,7 @@ __device__ __forceinline__ void lds_fft(cx<T>* buf, const cx<T>* tw, int tid, in
       pass_sync<MAP>();
     } else {
       fft_pass<T, PL, NB, NT, ES, BS, S, P, MAP, PADSH>(buf, tw, tid, b_act);
-      lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, P + 1>(buf, tw, tid, b_act);
+      lds_fft<T, PL, NB, NT, ES, BS, S, MAP, PADSH, KEEP, UNR, P + 1>(buf, tw, tid, b_act);
     }
   }
 }
@@ -894,7 +903,7 @@ __device__ __forceinline__ void fft_first_regs(cx<T>* buf, cx<T> (&v)[FirstPass<
 // read instead of calling store (which must then write LDS position pos of
 // sequence b, as it is still called by an MFMA last pass).
 template <typename T, class PL, int NB, int NT, int ES, int BS, int S, int MAP, int PADSH, bool SLOTS = false,
-          bool INPLACE = false, class Store>
+          bool INPLACE = false, int UNR = 1, class Store>
 __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, int b_act, Store&& store) {
   constexpr int NP = PL::np;
   if constexpr (NP > 1) {
@@ -908,7 +917,7 @@ __device__ __forceinline__ void fft_rest(cx<T>* buf, const cx<T>* tw, int tid, i
         vv.y = v.y;
         store(i, r, b, pos, vv);
       };
-      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH, decltype(st2)&, SLOTS>(
+      fft_pass_mfma_last<PL, NB, NT, ES, BS, S, PLAST, MAP, PADSH, decltype(st2)&, SLOTS, UNR>(
           reinterpret_cast<const float2*>(buf), reinterpret_cast<const float2*>(tw), tid, b_act, st2);
     } else {
       fft_last_valu<T, PL, NB, NT, ES, BS, S, MAP, PADSH, 0, INPLACE>(buf, tw, tid, b_act, store);

@@ -276,7 +276,9 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
     fft_first_regs<T, PL, C, NT, C, 1, S, 0, 0>(tile, v, tid, C, store);
     const int next = (int)xcd_item(blockIdx.x, G, k + 1, total);
     if (next >= 0) issue(decode(next));  // in flight during this item's LDS passes
-    fft_rest<T, PL, C, NT, C, 1, S, 0, 0>(tile, stw, tid, C, store);
+    // mixed plans: one-term passes overlap two MFMA groups (the three-term
+    // inverse pass would spill)
+    fft_rest<T, PL, C, NT, C, 1, S, 0, 0, false, false, (MAXT == 1 ? 2 : 1)>(tile, stw, tid, C, store);
     item = next;
   }
 }
@@ -544,6 +546,9 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   // lanes idle in every wave and the flux pass would lose a resident
   // workgroup to registers, nor with fewer fields than waves.
   constexpr bool WAVE = !MX && (MODE == RM_XA || MODE == RM_XB) && N >= 512 && NB >= NT / 64;
+  // MFMA groups overlapped in the mixed last pass (measured: the velocity
+  // pass 2, the flux pass 4 at N = 256; the others spill or slow down)
+  constexpr int UNR = MODE == RM_XA ? 2 : ((MODE == RM_XB && N <= 256) ? 4 : 1);
   constexpr int RMAP = WAVE ? 3 : 1;
   using FP = FirstPass<PL, NB, NT, RMAP>;
   auto at = [](int b, int pos) { return lds_at<1, BS, LAY, PL, 0>(b, pos); };
@@ -713,7 +718,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
       }
       fft_first_regs<T, PL, NB, NT, 1, BS, +1, FM1, LAY, ZROWS>(buf, v, tid, nin, lds_store);
       if (item + gridDim.x < nitems) issue(item + gridDim.x);  // next pair's loads overlap the rest
-      fft_rest<T, PL, NB, NT, 1, BS, +1, RMAP, LAY, false, true>(buf, stw, tid, nin, lds_store);
+      fft_rest<T, PL, NB, NT, 1, BS, +1, RMAP, LAY, false, true, UNR>(buf, stw, tid, nin, lds_store);
     }
     __syncthreads();
 
@@ -847,7 +852,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
 
     if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
       __syncthreads();
-      lds_fft<T, PL, NB, NT, 1, BS, -1, RMAP, LAY, K>(buf, stw, tid, nout);  // only k <= K and N - k are read
+      lds_fft<T, PL, NB, NT, 1, BS, -1, RMAP, LAY, K, UNR>(buf, stw, tid, nout);  // only k <= K and N - k are read
       // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
       T* out0 = member_ptr(a.out0, mem, a.bt.mstride);
       const int64_t ost = a.out_stride;
