@@ -649,7 +649,12 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     } else {
       // inverse x transform: first pass from the prefetched registers
       // first-pass inputs Z[q] = X0[q] + i X1[q] (q <= K),
-      // Z[N-k] = conj(X0[k]) + i conj(X1[k]) (k <= K), zero in the gap
+      // Z[N-k] = conj(X0[k]) + i conj(X1[k]) (k <= K), zero in the gap.
+      // Rows r < R/2 hold q < N/2, rows r >= R/2 hold q > N/2 (mirrors of
+      // q < N/2).  The prefetch registers are zero wherever nothing was loaded
+      // (q > K, or an idle slot), so both formulas give zero in the gap with no
+      // case analysis.  (At q = 0 the formula also adds the imaginary parts of
+      // the two rows' DC terms, which are zero up to rounding.)
       cx<T> v[FP::CNT][FP::R];
 #pragma unroll
       for (int i = 0; i < FP::CNT; ++i) {
@@ -664,56 +669,48 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
             v[i][r] = mk<T>(0, 0);
             continue;
           }
-          const int q = j + r * FP::NBF;
-          cx<T> x0 = mk<T>(0, 0), x1 = mk<T>(0, 0);
           if (r < RH) {
-            x0 = p0[i][r < RH ? r : 0];
-            x1 = p1[i][r < RH ? r : 0];
+            const cx<T> x0 = p0[i][r < RH ? r : 0], x1 = p1[i][r < RH ? r : 0];
+            v[i][r] = mk<T>(x0.x - x1.y, x0.y + x1.x);
+            continue;
           }
-          cx<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+          // mirror element X[N - q]: element R-r-1 of butterfly NBF-j, or, for
+          // j = 0, element R-r of the same butterfly (none for r = R/2: that is
+          // q = N/2, in the gap)
+          const int r1 = (FP::R - 1 - r) < RH ? (FP::R - 1 - r) : 0;
+          const bool self_ok = (FP::R - r) < RH;
+          const int r0 = self_ok ? (FP::R - r) : 0;
+          const cx<T> zero = mk<T>(0, 0);
+          const cx<T> self0 = self_ok ? p0[i][r0] : zero, self1 = self_ok ? p1[i][r0] : zero;
+          cx<T> x0 = zero, x1 = zero;
           if constexpr (FMAP == 3) {
-            if (r >= RH) {  // uniform: every lane takes part in the shuffles
-              const int r1 = (FP::R - 1 - r) < RH ? (FP::R - 1 - r) : 0;
-              s0 = mk<T>(__shfl(p0[i][r1].x, plane), __shfl(p0[i][r1].y, plane));
-              s1 = mk<T>(__shfl(p1[i][r1].x, plane), __shfl(p1[i][r1].y, plane));
-            }
-          }
-          if (ok && q >= N - K) {  // only r >= R/2 reach here (j < NBF, K < N/3)
-            if constexpr (FMAP == 3) {
-              // N - q is element R-r-1 of butterfly NBF-j (partner lane), or,
-              // for j = 0, element R-r of the same butterfly
-              const int r0 = (FP::R - r) < RH ? (FP::R - r) : 0;
-              x0 = j == 0 ? p0[i][r0] : s0;
-              x1 = j == 0 ? p1[i][r0] : s1;
-            } else if constexpr (FMAP == 2) {
-              // N - q is element R-r-1 of butterfly NBF-j (the partner slot),
-              // or, for j = 0, element R-r of the same butterfly, or, for
-              // j = NBF/2, element R-r-1 of the same butterfly
-              const int ip = i < HC ? i + HC : i - HC;
-              const int r1 = (FP::R - 1 - r) < RH ? (FP::R - 1 - r) : 0;
-              const int r0 = (FP::R - r) < RH ? (FP::R - r) : 0;
-              if (j == 0) {
-                x0 = p0[i][r0];
-                x1 = p1[i][r0];
-              } else if (j == FP::NBF / 2) {
-                x0 = p0[i][r1];
-                x1 = p1[i][r1];
-              } else {
-                x0 = p0[ip][r1];
-                x1 = p1[ip][r1];
-              }
+            // uniform: every lane takes part in the shuffles
+            const cx<T> s0 = mk<T>(__shfl(p0[i][r1].x, plane), __shfl(p0[i][r1].y, plane));
+            const cx<T> s1 = mk<T>(__shfl(p1[i][r1].x, plane), __shfl(p1[i][r1].y, plane));
+            x0 = j == 0 ? self0 : s0;
+            x1 = j == 0 ? self1 : s1;
+          } else if constexpr (FMAP == 2) {
+            // the partner butterfly is the partner slot, except j = 0 (see
+            // above) and j = NBF/2, its own partner
+            const int ip = i < HC ? i + HC : i - HC;
+            if (j == 0) {
+              x0 = self0;
+              x1 = self1;
+            } else if (j == FP::NBF / 2) {
+              x0 = p0[i][r1];
+              x1 = p1[i][r1];
             } else {
+              x0 = p0[ip][r1];
+              x1 = p1[ip][r1];
+            }
+          } else {
+            const int q = j + r * FP::NBF;
+            if (ok && q >= N - K) {
               x0 = ld(src, row0 * NHP + (N - q));
               x1 = ld(src, (row0 + 1) * NHP + (N - q));
             }
           }
-          cx<T> z = mk<T>(0, 0);
-          if (ok) {
-            if (q == 0) z = mk<T>(x0.x, x1.x);
-            else if (q <= K) z = mk<T>(x0.x - x1.y, x0.y + x1.x);
-            else if (q >= N - K) z = mk<T>(x0.x + x1.y, x1.x - x0.y);
-          }
-          v[i][r] = z;
+          v[i][r] = mk<T>(x0.x + x1.y, x1.x - x0.y);
         }
       }
       fft_first_regs<T, PL, NB, NT, 1, BS, +1, FM1, LAY, ZROWS>(buf, v, tid, nin, lds_store);
