@@ -455,6 +455,15 @@ template <> struct RowShape<RM_XDIAG> { static constexpr int NIN = kDiagFields, 
 template <typename T>
 __device__ __forceinline__ bool finite_(T v) { return isfinite(v); }
 
+// 1/x and sqrt(x) of the pointwise stages.  FP32: the hardware v_rcp_f32 and
+// v_sqrt_f32 (1 ulp) instead of the correctly rounded sequences (about ten
+// instructions each), in the VALU-bound flux and velocity passes; the
+// difference is at the level of FP32 rounding.  FP64: correctly rounded.
+template <typename T> __device__ __forceinline__ T recip_(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float recip_<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename T> __device__ __forceinline__ T sqrt_(T x) { return sqrt(x); }
+template <> __device__ __forceinline__ float sqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Fixed-order tree reduction over the block (sum, or NaN-propagating max);
 // the result is valid in thread 0.  Deterministic for a given launch shape.
 template <int NT = kThreads>
@@ -739,7 +748,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
       // u = m / rho, both rows at once
       for (int x = tid; x < N; x += NT) {
         const cx<T> rho = buf[at(0, x)];
-        const T i0 = T(1) / rho.x, i1 = T(1) / rho.y;
+        const T i0 = recip_(rho.x), i1 = recip_(rho.y);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           const cx<T> m = buf[at(1 + i, x)];
@@ -768,7 +777,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           const T Sxx = g(8), Syy = g(9), Sxy = g(10), Sxz = g(11), Syz = g(12);
           const T Szz = -(Sxx + Syy);
           const T Jx = g(13), Jy = g(14), Jz = g(15);
-          const T ir = T(1) / rho;
+          const T ir = recip_(rho);
           const T ux = mx * ir, uy = my * ir, uz = mz * ir;
           const T B2 = Bx * Bx + By * By + Bz * Bz;
           const T P = gm1 * (E - T(0.5) * (mx * ux + my * uy + mz * uz) - T(0.5) * B2);
@@ -799,7 +808,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           }
           // fastest signal speed for the CFL limit, and a non-finite check
           const T umax = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
-          const T c = umax + sqrt((gam * P + B2) * ir);
+          const T c = umax + sqrt_((gam * P + B2) * ir);
           if (!(c <= cfl)) cfl = c;  // NaN propagates
           const bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) &&
                            finite_(By) && finite_(Bz) && finite_(E);
