@@ -448,9 +448,13 @@ struct Engine {
   }
 
   // Copy-only y passes of `count` fields from slot lists.
+  // y pass that copies (transforms) each field.  The row passes leave their
+  // r2c outputs doubled, and the forward y pass, their only reader, halves
+  // them.
   void y_copy(int kind, int count, T* const* ins, T* const* outs) {
     OutSpec sp[kMaxOut];
-    for (int f = 0; f < count; ++f) sp[f] = copy_spec(f, 1.0);
+    const double coef = kind == PK_YFWD ? 0.5 : 1.0;
+    for (int f = 0; f < count; ++f) sp[f] = copy_spec(f, coef);
     col(kind, count, ins, count, outs, sp);
   }
 

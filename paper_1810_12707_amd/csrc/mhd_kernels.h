@@ -859,14 +859,17 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     if constexpr (MODE == RM_XA || MODE == RM_XB || MODE == RM_XFWD_REAL) {
       __syncthreads();
       lds_fft<T, PL, NB, NT, 1, BS, -1, RMAP, LAY, K, UNR>(buf, stw, tid, nout);  // only k <= K and N - k are read
-      // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K
+      // unpack: X0[k] = (Z[k] + conj Z[N-k]) / 2, X1[k] = -i (Z[k] - conj Z[N-k]) / 2, k = 0..K,
+      // stored doubled (2 X0, 2 X1): the forward y pass that reads these rows
+      // applies the 1/2 with its copy coefficient (an exact power-of-two
+      // scaling, so the values are the same)
       T* out0 = member_ptr(a.out0, mem, a.bt.mstride);
       const int64_t ost = a.out_stride;
       auto unpack = [&](int fld, int k) {
         const cx<T> zk = buf[at(fld, k)];
         const cx<T> zm = buf[at(fld, k == 0 ? 0 : N - k)];
-        const cx<T> x0 = mk<T>(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
-        const cx<T> x1 = mk<T>(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
+        const cx<T> x0 = mk<T>(zk.x + zm.x, zk.y - zm.y);
+        const cx<T> x1 = mk<T>(zk.y + zm.y, zm.x - zk.x);
         T* dst = out0 + 2 * fld * ost;
         st(dst, row0 * NHP + k, x0);
         st(dst, (row0 + 1) * NHP + k, x1);
