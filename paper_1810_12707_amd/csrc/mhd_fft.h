@@ -233,6 +233,14 @@ template <class PL> constexpr int plan_ns(int p) {
   return ns;
 }
 
+// A mixed plan with a radix-16 stage before its last (an LDS-to-LDS MFMA pass).
+template <class PL> constexpr bool mid_mfma() {
+  if (!PL::MX) return false;
+  for (int i = 0; i + 1 < PL::np; ++i)
+    if (PL::r[i] == 16) return true;
+  return false;
+}
+
 template <class PL> constexpr bool plan_ok() {
   int prod = 1;
   for (int i = 0; i < PL::np; ++i) prod *= PL::r[i];
@@ -640,7 +648,6 @@ template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int P
           int UNR = 1>
 __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const float2* tw, int tid, int b_act,
                                                    Store&& store) {
-  static_assert(!wave_map<MAP>(), "MFMA passes use the workgroup lane maps");
   constexpr int N = PL::N;
   constexpr int R = 16;
   constexpr int NS = plan_ns<PL>(P);
@@ -649,17 +656,28 @@ __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const floa
   constexpr int TOT = NB * NBF;
   constexpr int NGRP = (TOT + 15) / 16;
   constexpr int NW = NT / 64;
-  constexpr int GPW = (NGRP + NW - 1) / NW;
+  // groups per wave: workgroup maps deal the groups round-robin over the
+  // waves; wave maps give each wave the groups of its own sequences
+  constexpr int GPW = wave_map<MAP>() ? (seqs_per_wave<NB, NT>() * NBF + 15) / 16 : (NGRP + NW - 1) / NW;
   const int lane = tid & 63, wv = tid >> 6;
   const int n = lane & 15, g = lane >> 4;
   bf16x8 a0h, a0l, a1h, a1l;
   dft16_operands<S>(lane, a0h, a0l, a1h, a1l);
   auto group = [&](int s) {
-    const int grp = wv + s * NW;
-    const int w = grp * 16 + n;
     int b, j;
-    lane_map<NB, NBF, MAP>(w, b, j);
-    const bool ok = grp < NGRP && w < TOT && b < b_act;
+    bool ok;
+    if constexpr (wave_map<MAP>()) {
+      const int u = s * 16 + n;  // butterfly index over the wave's sequences
+      const int fl = u / NBF;
+      j = u - fl * NBF;
+      b = fl * NW + wv;
+      ok = fl < seqs_per_wave<NB, NT>() && b < b_act;
+    } else {
+      const int grp = wv + s * NW;
+      const int w = grp * 16 + n;
+      lane_map<NB, NBF, MAP>(w, b, j);
+      ok = grp < NGRP && w < TOT && b < b_act;
+    }
     bf16x8 xh, xl;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {

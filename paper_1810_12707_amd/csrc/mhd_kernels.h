@@ -547,14 +547,17 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   // row, so that a 32-lane read spanning two rows of N = 128 uses all banks
   constexpr int BS = SWZ ? N + 16 : N + (N >> PADSH) + 1;
   constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
-  // From N = 512 the velocity and flux passes (VALU plans) keep each field's
-  // transforms inside one wave (wave maps): between their passes a wave-level
+  // From N = 512 the velocity and flux passes keep each field's transforms
+  // inside one wave (wave maps; in the mixed velocity pass the MFMA groups of
+  // the last pass are the wave's own butterflies too, 7% faster; the mixed
+  // flux pass was slower so): between their passes a wave-level
   // fence replaces the workgroup barrier, and only the pointwise stage, which
   // reads every field at one point, is bracketed by barriers (12% and 5%
   // faster at N = 512).  Not at N = 256, where half-wide passes would leave
   // lanes idle in every wave and the flux pass would lose a resident
   // workgroup to registers, nor with fewer fields than waves.
-  constexpr bool WAVE = !MX && (MODE == RM_XA || MODE == RM_XB) && N >= 512 && NB >= NT / 64;
+  constexpr bool WAVE = (MX ? (MODE == RM_XA && !mid_mfma<PL>()) : (MODE == RM_XA || MODE == RM_XB)) && N >= 512 &&
+                       NB >= NT / 64;
   // MFMA groups overlapped in the mixed last pass (measured: the velocity
   // pass 2, the flux pass 4 at N = 256; the others spill or slow down)
   constexpr int UNR = MODE == RM_XA ? 2 : ((MODE == RM_XB && N <= 256) ? 4 : 1);
