@@ -494,12 +494,14 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s,
 // words: an unsigned max over the bit patterns of non-negative floats orders
 // them like the floats (NaN sorts above every finite value), and integer adds
 // commute, so the result does not depend on block order.  Block-uniform call.
+// s_red: NT doubles of LDS scratch, which may alias the caller's row buffer
+// (the reductions begin and end with a barrier).
 template <int NT, typename T>
-__device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status) {
-  __shared__ double s_red[NT];
+__device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status, double* s_red) {
   const int tid = threadIdx.x;
   const double cfl_b = block_reduce<NT>(double(cfl), true, s_red, tid);
   const double bad_b = block_reduce<NT>(double(bad), false, s_red, tid);
+  __syncthreads();  // every thread has read the results before the scratch is reused
   if (tid == 0) {
     const float cf = float(cfl_b);
     const unsigned bits = (cf != cf) ? 0x7fc00000u : (cf > 0.f ? __float_as_uint(cf) : 0u);
@@ -509,8 +511,13 @@ __device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status) {
 }
 
 // Threads of a row pass: FP32 rows of N >= 1024 take 512, which keeps the
-// per-thread first-pass work (and registers) of N = 512 on 256 threads.
+// per-thread first-pass work (and registers) of N = 512 on 256 threads.  The
+// FP32 flux pass at N = 512 also takes 512: with wave maps each wave then
+// owns two fields instead of four, the registers fit 128, and its LDS tile
+// still allows two workgroups per CU, so four waves per SIMD run instead of
+// two (13% faster).
 template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
+  if (sizeof(T) == 4 && !MX && MODE == RM_XB && N == 512) return 2 * kThreads;
   return (sizeof(T) == 4 && N >= 1024) ? 2 * kThreads : kThreads;
 }
 
@@ -519,6 +526,7 @@ template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
 // 256 registers and then runs one wave per SIMD (the MFMA variant at N = 512
 // was 1.3x slower so than capped with a small spill).
 template <typename T, int N, int MODE, bool MX> constexpr int row_min_blocks() {
+  if (sizeof(T) == 4 && !MX && MODE == RM_XB && N == 512) return 2;  // 4 waves per SIMD
   return sizeof(T) == 4 ? 2 * kThreads / row_threads<T, N, MODE, MX>() : 1;
 }
 
@@ -566,6 +574,12 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   auto at = [](int b, int pos) { return lds_at<1, BS, LAY, PL, 0>(b, pos); };
   __shared__ cx<T> buf[NB * BS];
   __shared__ cx<T> stw[N];
+  // block reductions (status words, diagnostics) use the row buffer as scratch
+  // when it is large enough (each begins with a barrier, after which no row
+  // work touches the buffer); small sizes get their own array
+  constexpr bool RED_IN_BUF = sizeof(cx<T>) * NB * BS >= NT * sizeof(double);
+  __shared__ double red_own[RED_IN_BUF ? 1 : NT];
+  double* const red = RED_IN_BUF ? reinterpret_cast<double*>(buf) : red_own;
   const int tid = threadIdx.x;
   const int64_t rows_per_mem = (int64_t)N * N / 2;
   const int64_t nitems = rows_per_mem * a.bt.nmem;
@@ -632,7 +646,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     if constexpr (MODE == RM_XB) {
       if (mem != cur_m) {  // uniform across the workgroup
         if (cur_m >= 0) {
-          flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
+          flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
           cfl = T(0);
           bad = 0;
         }
@@ -893,12 +907,11 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   }
 
   if constexpr (MODE == RM_XB) {
-    if (cur_m >= 0) flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride));
+    if (cur_m >= 0) flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
   }
   if constexpr (MODE == RM_XDIAG) {
-    __shared__ double s_red[NT];
     for (int i = 0; i < kDiagQ; ++i) {
-      const double r = block_reduce<NT>(q[i], i == DQ_DIVB_MAX || i == DQ_CFL_MAX, s_red, tid);
+      const double r = block_reduce<NT>(q[i], i == DQ_DIVB_MAX || i == DQ_CFL_MAX, red, tid);
       if (tid == 0) a.partials[(int64_t)blockIdx.x * kDiagQ + i] = r;
     }
   }
