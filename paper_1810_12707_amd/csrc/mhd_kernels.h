@@ -512,12 +512,12 @@ __device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status, d
 
 // Threads of a row pass: FP32 rows of N >= 1024 take 512, which keeps the
 // per-thread first-pass work (and registers) of N = 512 on 256 threads.  The
-// FP32 flux pass at N = 512 also takes 512: with wave maps each wave then
-// owns two fields instead of four, the registers fit 128, and its LDS tile
-// still allows two workgroups per CU, so four waves per SIMD run instead of
-// two (13% faster).
+// FP32 flux pass at N = 512 and 256 also takes 512: with wave maps each wave
+// then owns two fields instead of four, the registers fit 128, and its LDS
+// tile still allows two workgroups per CU, so four waves per SIMD run instead
+// of two (13% faster at 512) or three (3% at 256).
 template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
-  if (sizeof(T) == 4 && !MX && MODE == RM_XB && N == 512) return 2 * kThreads;
+  if (sizeof(T) == 4 && !MX && MODE == RM_XB && (N == 512 || N == 256)) return 2 * kThreads;
   return (sizeof(T) == 4 && N >= 1024) ? 2 * kThreads : kThreads;
 }
 
@@ -526,7 +526,7 @@ template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
 // 256 registers and then runs one wave per SIMD (the MFMA variant at N = 512
 // was 1.3x slower so than capped with a small spill).
 template <typename T, int N, int MODE, bool MX> constexpr int row_min_blocks() {
-  if (sizeof(T) == 4 && !MX && MODE == RM_XB && N == 512) return 2;  // 4 waves per SIMD
+  if (sizeof(T) == 4 && !MX && MODE == RM_XB && (N == 512 || N == 256)) return 2;  // 4 waves per SIMD
   return sizeof(T) == 4 ? 2 * kThreads / row_threads<T, N, MODE, MX>() : 1;
 }
 
@@ -558,14 +558,15 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   // From N = 512 the velocity and flux passes keep each field's transforms
   // inside one wave (wave maps; in the mixed velocity pass the MFMA groups of
   // the last pass are the wave's own butterflies too, 7% faster; the mixed
-  // flux pass was slower so): between their passes a wave-level
+  // flux pass was slower so; the FP32 flux pass at N = 256 too, with 512
+  // threads): between their passes a wave-level
   // fence replaces the workgroup barrier, and only the pointwise stage, which
   // reads every field at one point, is bracketed by barriers (12% and 5%
-  // faster at N = 512).  Not at N = 256, where half-wide passes would leave
-  // lanes idle in every wave and the flux pass would lose a resident
-  // workgroup to registers, nor with fewer fields than waves.
-  constexpr bool WAVE = (MX ? (MODE == RM_XA && !mid_mfma<PL>()) : (MODE == RM_XA || MODE == RM_XB)) && N >= 512 &&
-                       NB >= NT / 64;
+  // faster at N = 512).  Not for the velocity pass at N = 256, where
+  // half-wide passes would leave lanes idle in every wave, nor with fewer
+  // fields than waves.
+  constexpr bool WAVE = (MX ? (MODE == RM_XA && !mid_mfma<PL>()) : (MODE == RM_XA || MODE == RM_XB)) &&
+                       (N >= 512 || (!MX && MODE == RM_XB && N == 256)) && NB >= NT / 64;
   // MFMA groups overlapped in the mixed last pass (measured: the velocity
   // pass 2, the flux pass 4 at N = 256; the others spill or slow down)
   constexpr int UNR = MODE == RM_XA ? 2 : ((MODE == RM_XB && N <= 256) ? 4 : 1);
