@@ -59,16 +59,16 @@ template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs
 // half lines, whose other halves another workgroup reads later, often after
 // eviction), and enough threads that each holds one or two first-pass
 // butterflies.  Measured per pass class: one butterfly per thread (fewer
-// registers, more resident waves) pays for the three-term inverse pass at
-// N = 256 and 512 and for the forward passes at N = 512; the one-term
-// inverse passes run best with two.  Above 512 (LDS-limited to one
+// registers, more resident waves) pays for the inverse passes at N = 256 and
+// 512 and for the forward passes at N = 512; the forward passes at N = 256
+// run best with two.  Above 512 (LDS-limited to one
 // workgroup per CU) 512 threads on 8 columns avoid register spills.  The
 // MFMA variant follows the same rule from N = 512 up and keeps 256 threads
 // below (measured).
 template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
   if (sizeof(T) != 4 || (MX && N < 512)) return kThreads;
-  if (N == 256) return MAXT > 1 ? 2 * kThreads : kThreads;
-  if (N == 512) return (MAXT > 1 || S < 0) ? 4 * kThreads : 2 * kThreads;
+  if (N == 256) return (MAXT > 1 || S > 0) ? 2 * kThreads : kThreads;
+  if (N == 512) return 4 * kThreads;
   return N > 512 ? 2 * kThreads : kThreads;
 }
 template <typename T, int N, bool MX> constexpr int col_tile() {
