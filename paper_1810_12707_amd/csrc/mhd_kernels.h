@@ -63,10 +63,10 @@ template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs
 // 512 and for the forward passes at N = 512; the forward passes at N = 256
 // run best with two.  Above 512 (LDS-limited to one
 // workgroup per CU) 512 threads on 8 columns avoid register spills.  The
-// MFMA variant follows the same rule from N = 512 up and keeps 256 threads
-// below (measured).
+// MFMA variant follows the same rule from N = 512 up and for the three-term
+// pass at 256, and keeps 256 threads otherwise (measured).
 template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
-  if (sizeof(T) != 4 || (MX && N < 512)) return kThreads;
+  if (sizeof(T) != 4 || (MX && N < 256) || (MX && N == 256 && MAXT == 1)) return kThreads;
   if (N == 256) return (MAXT > 1 || S > 0) ? 2 * kThreads : kThreads;
   if (N == 512) return 4 * kThreads;
   return N > 512 ? 2 * kThreads : kThreads;
