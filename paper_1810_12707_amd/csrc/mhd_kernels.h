@@ -521,12 +521,14 @@ template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
   return (sizeof(T) == 4 && N >= 1024) ? 2 * kThreads : kThreads;
 }
 
-// FP32 row passes (MFMA variant included) are held to two waves per SIMD,
-// which is what their LDS allows: left free, the flux pass can take more than
-// 256 registers and then runs one wave per SIMD (the MFMA variant at N = 512
-// was 1.3x slower so than capped with a small spill).
+// Register caps of the FP32 row passes (MFMA variant included), as resident
+// workgroups per CU: two, i.e. two waves per SIMD at 256 threads and four for
+// the 512-thread flux pass at N = 256 and 512 (128 registers), which is what
+// their LDS allows.  Left free, the flux pass can take more than 256 registers
+// and then runs one wave per SIMD (the MFMA variant at N = 512 was 1.3x
+// slower so than capped).
 template <typename T, int N, int MODE, bool MX> constexpr int row_min_blocks() {
-  if (sizeof(T) == 4 && !MX && MODE == RM_XB && (N == 512 || N == 256)) return 2;  // 4 waves per SIMD
+  if (sizeof(T) == 4 && !MX && MODE == RM_XB && (N == 512 || N == 256)) return 2;
   return sizeof(T) == 4 ? 2 * kThreads / row_threads<T, N, MODE, MX>() : 1;
 }
 
@@ -555,16 +557,15 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   // row, so that a 32-lane read spanning two rows of N = 128 uses all banks
   constexpr int BS = SWZ ? N + 16 : N + (N >> PADSH) + 1;
   constexpr bool SPEC_IN = MODE != RM_XFWD_REAL;
-  // From N = 512 the velocity and flux passes keep each field's transforms
-  // inside one wave (wave maps; in the mixed velocity pass the MFMA groups of
-  // the last pass are the wave's own butterflies too, 7% faster; the mixed
-  // flux pass was slower so; the FP32 flux pass at N = 256 too, with 512
-  // threads): between their passes a wave-level
-  // fence replaces the workgroup barrier, and only the pointwise stage, which
-  // reads every field at one point, is bracketed by barriers (12% and 5%
-  // faster at N = 512).  Not for the velocity pass at N = 256, where
-  // half-wide passes would leave lanes idle in every wave, nor with fewer
-  // fields than waves.
+  // Wave maps: each field's transforms stay inside one wave, so a wave-level
+  // fence replaces the workgroup barrier between passes and only the
+  // pointwise stage, which reads every field at one point, is bracketed by
+  // barriers.  Used (measured) by the velocity and flux passes from N = 512
+  // (12% and 5% faster), the FP32 flux pass at 256 (with 512 threads) and the
+  // mixed velocity pass from 512, whose last-pass MFMA groups then take the
+  // wave's own butterflies (7%); not by the mixed flux pass (slower), the
+  // velocity pass at 256 (half-wide passes would idle lanes in every wave) or
+  // with fewer fields than waves.
   constexpr bool WAVE = (MX ? (MODE == RM_XA && !mid_mfma<PL>()) : (MODE == RM_XA || MODE == RM_XB)) &&
                        (N >= 512 || (!MX && MODE == RM_XB && N == 256)) && NB >= NT / 64;
   // MFMA groups overlapped in the mixed last pass (measured: the velocity

@@ -20,6 +20,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -28,12 +29,21 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 
 
+def _code_only(text: str) -> str:
+    """C++ source with comments and blank lines removed (comment edits do not
+    change the kernels, so they should not invalidate recorded counters)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+
+
 def source_sha256() -> str:
-    """Hash of every kernel and host source file (sorted by name)."""
+    """Hash of the code (comments stripped) of every kernel and host source
+    file, sorted by name."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(CSRC, name), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
