@@ -55,3 +55,13 @@ def test_copy_factor(tmp_path):
     path = tmp_path / "copy.csv"
     write_csv(path, [("fill", "FETCH_SIZE", 3.0), ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 512.0 * 1024)])
     assert abs(P.copy_factor(str(path), "FETCH_SIZE", 1024) - 0.5) < 1e-12
+
+
+def test_code_only_ignores_comments_but_not_code():
+    from paper_1810_12707_amd.profile_summary import _code_only
+
+    a = "int x = 1;  // one\n/* block\n   comment */\nint y = 2;\n\n"
+    b = "// header\nint x = 1;\nint y = 2; /* trailing */\n"
+    c = "int x = 1;\nint y = 3;\n"
+    assert _code_only(a) == _code_only(b)
+    assert _code_only(a) != _code_only(c)
