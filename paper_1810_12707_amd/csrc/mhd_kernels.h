@@ -515,9 +515,12 @@ __device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status, d
 // FP32 flux pass at N = 512 and 256 also takes 512: with wave maps each wave
 // then owns two fields instead of four, the registers fit 128, and its LDS
 // tile still allows two workgroups per CU, so four waves per SIMD run instead
-// of two (13% faster at 512) or three (3% at 256).
+// of two (13% faster at 512) or three (3% at 256).  The FP32 velocity pass at
+// N = 256 takes 128: two waves of two fields each, whose 32-butterfly radix-8
+// passes then fill every lane (256 threads left half of them idle; 19%).
 template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
   if (sizeof(T) == 4 && !MX && MODE == RM_XB && (N == 512 || N == 256)) return 2 * kThreads;
+  if (sizeof(T) == 4 && !MX && MODE == RM_XA && N == 256) return kThreads / 2;
   return (sizeof(T) == 4 && N >= 1024) ? 2 * kThreads : kThreads;
 }
 
@@ -561,13 +564,12 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   // fence replaces the workgroup barrier between passes and only the
   // pointwise stage, which reads every field at one point, is bracketed by
   // barriers.  Used (measured) by the velocity and flux passes from N = 512
-  // (12% and 5% faster), the FP32 flux pass at 256 (with 512 threads) and the
-  // mixed velocity pass from 512, whose last-pass MFMA groups then take the
-  // wave's own butterflies (7%); not by the mixed flux pass (slower), the
-  // velocity pass at 256 (half-wide passes would idle lanes in every wave) or
-  // with fewer fields than waves.
+  // (12% and 5% faster), the FP32 velocity and flux passes at 256 (with 128
+  // and 512 threads) and the mixed velocity pass from 512, whose last-pass
+  // MFMA groups then take the wave's own butterflies (7%); not by the mixed
+  // flux pass (slower) or with fewer fields than waves.
   constexpr bool WAVE = (MX ? (MODE == RM_XA && !mid_mfma<PL>()) : (MODE == RM_XA || MODE == RM_XB)) &&
-                       (N >= 512 || (!MX && MODE == RM_XB && N == 256)) && NB >= NT / 64;
+                       (N >= 512 || (!MX && N == 256)) && NB >= NT / 64;
   // MFMA groups overlapped in the mixed last pass (measured: the velocity
   // pass 2, the flux pass 4 at N = 256; the others spill or slow down)
   constexpr int UNR = MODE == RM_XA ? 2 : ((MODE == RM_XB && N <= 256) ? 4 : 1);
