@@ -157,3 +157,54 @@ def test_diagnostics_match_oracle(prec):
     for i, k in enumerate(("mom_x", "mom_y", "mom_z")):
         assert abs(d["mom"][i] - ref[k]) <= tol * max(1.0, abs(ref[k]))
     S.close()
+
+
+def test_status_codes_of_a_single_run():
+    """The status paths of mhd_step / mhd_diagnostics: no state yet, a step
+    above and below the CFL limit (with and without the check flag), and a
+    non-finite value in the state (before and after a step)."""
+    from paper_1810_12707_amd.mhd import MHD_E_CFL, MHD_E_NONFINITE, MHD_E_STATE, MHD_FLAG_CHECK_CFL, MHDError
+
+    log("[status] n=24 fp32")
+    c = I.random_turbulence(24, b_rms=0.3, seeds=(51, 52, 53))
+    lim = O.diag(c.U, c.gamma, c.nu, c.eta, cfl=0.1)["dt_cfl"]
+    kw = dict(gamma=c.gamma, nu=c.nu, eta=c.eta, cfl=0.1)
+
+    S = solver(24, "fp32", dt=0.5 * lim, flags=MHD_FLAG_CHECK_CFL, **kw)
+    with pytest.raises(MHDError) as e:
+        S.step(1)
+    assert e.value.status == MHD_E_STATE
+    S.set_state(dev(c.U, torch.float64))
+    S.step(2)
+    rc, d = S.diagnostics()
+    log("  dt = 0.5 limit, checked:", rc)
+    assert rc == 0 and d["nonfinite"] == 0
+    S.close()
+
+    for flags, want in ((MHD_FLAG_CHECK_CFL, MHD_E_CFL), (0, 0)):
+        S = solver(24, "fp32", dt=3.0 * lim, flags=flags, **kw)
+        S.set_state(dev(c.U, torch.float64))
+        rc, _ = S.diagnostics()
+        assert rc == 0  # no step has run yet
+        S.step(1)
+        rc, d = S.diagnostics()
+        log(f"  dt = 3 limit, flags {flags}:", rc)
+        assert rc == want and d["nonfinite"] == 0
+        # a new state clears what the steps saw
+        S.set_state(dev(c.U, torch.float64))
+        rc, _ = S.diagnostics()
+        assert rc == 0
+        S.close()
+
+    bad = c.U.copy()
+    bad[0, 5, 6, 7] = np.nan
+    S = solver(24, "fp32", dt=0.5 * lim, flags=MHD_FLAG_CHECK_CFL, **kw)
+    S.set_state(dev(bad, torch.float64))
+    rc, d = S.diagnostics()
+    log("  NaN in rho, before a step:", rc, d["nonfinite"])
+    assert rc == MHD_E_NONFINITE and d["nonfinite"] > 0
+    S.step(1)
+    rc, _ = S.diagnostics()
+    log("  after a step:", rc)
+    assert rc == MHD_E_NONFINITE
+    S.close()
