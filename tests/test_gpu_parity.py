@@ -208,3 +208,37 @@ def test_status_codes_of_a_single_run():
     log("  after a step:", rc)
     assert rc == MHD_E_NONFINITE
     S.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [24, 32])
+def test_degenerate_states(n, prec):
+    """Degenerate cases of the method: a uniform state in motion (every flux
+    constant, so every derivative and the RHS vanish; the oracle agrees), and
+    zero steps (the state is left bit for bit)."""
+    log(f"[degenerate] n={n} prec={prec}")
+    dt_ = PREC[prec][0]
+    gamma, P0, B0, u0 = 5.0 / 3.0, 0.6, (0.3, -0.2, 0.5), (0.7, 0.1, -0.4)
+    U = np.zeros((8, n, n, n))
+    U[0] = 1.3
+    for i in range(3):
+        U[1 + i] = 1.3 * u0[i]
+        U[4 + i] = B0[i]
+    U[7] = P0 / (gamma - 1) + 0.5 * 1.3 * sum(v * v for v in u0) + 0.5 * sum(b * b for b in B0)
+    ref = O.rhs(U, gamma, 1e-2, 1e-2)
+    scale = np.abs(U).max()
+    assert np.abs(ref).max() <= 1e-12 * scale * n
+    S = solver(n, prec, gamma=gamma, nu=1e-2, eta=1e-2, dt=1e-3)
+    R = S.rhs(dev(U, dt_)).cpu().numpy()
+    eps = 1e-13 if prec == "fp64" else 1e-5
+    log(f"  max |rhs| {np.abs(R).max():.3e} (state scale {scale:.2f})")
+    assert np.abs(R).max() <= eps * scale * n
+    S.set_state(dev(U, torch.float64))
+    before = S.get_state().cpu().numpy()
+    S.step(0)
+    assert np.array_equal(S.get_state().cpu().numpy(), before)
+    S.step(3)
+    after = S.get_state().cpu().numpy()
+    log(f"  3 steps: max change {np.abs(after - before).max():.3e}")
+    assert np.abs(after - before).max() <= 3 * 1e-3 * eps * scale * n + (1e-14 if prec == "fp64" else 1e-6) * scale
+    S.close()
