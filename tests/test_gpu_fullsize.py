@@ -216,11 +216,18 @@ def test_rhs_exact_lowmode_state(n, prec):
     S.close()
 
 
-@pytest.mark.parametrize("case_name,n", [("turb", 256), ("abc", 512)])
-def test_ten_steps_conserve(case_name, n):
-    log(f"[fullsize steps] {case_name} n={n}")
+@pytest.mark.parametrize("case_name,n,prec", [("turb", 256, "fp32"), ("abc", 512, "fp32"), ("turb", 256, "mixed"),
+                                              ("abc", 512, "mixed")])
+def test_ten_steps_conserve(case_name, n, prec):
+    """The k = 0 right-hand sides of rho, m and E vanish identically, whatever
+    the transforms' rounding, so the means hold at FP32 rounding on both
+    paths.  div B of the state sits at the transforms' own error level (the
+    forward transform of the initial fields already puts it there: ~1e-6 of
+    the current in FP32, 4e-5 to 7e-5 on the mixed path, under its transform
+    bound 2e-4) and the curl-form induction update must not make it grow."""
+    log(f"[fullsize steps] {case_name} n={n} prec={prec}")
     c = I.config_turb256(n) if case_name == "turb" else I.config_dynamo512(n)
-    S = solver(n, "fp32", gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt)
+    S = solver(n, prec, gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt)
     S.set_state(torch.from_numpy(c.U).to("cuda:0"))
     rc0, d0 = S.diagnostics()
     S.step(10)
@@ -233,5 +240,6 @@ def test_ten_steps_conserve(case_name, n):
     scale = np.sqrt(2 * d0["e_kin"] * d0["mass"])  # ~ rms |m|
     for i in range(3):
         assert abs(d1["mom"][i] - d0["mom"][i]) <= 1e-6 * scale
-    assert d1["divb_rel"] <= 1e-5
+    assert d1["divb_rel"] <= (1e-5 if prec == "fp32" else 2e-4)
+    assert d1["divb_rel"] <= 1.5 * d0["divb_rel"] + 1e-7
     S.close()
