@@ -85,3 +85,69 @@ def test_nonfinite_count():
     U[3, 1, 2, 3] = np.nan
     U[7, 0, 0, 0] = np.inf
     assert O.diag(U, c.gamma)["nonfinite"] == 2
+
+
+def _cp_wave_diag(rho0, b0, B0=1.0, P0=0.7, n=12, axis=2):
+    from tests.test_oracle_rhs import cp_alfven
+
+    U = cp_alfven(n, 0.0, axis=axis, k=1, B0=B0, b0=b0, rho0=rho0, P0=P0)
+    return U, O.diag(U, 5.0 / 3.0)
+
+
+def test_cross_helicity_closed_form_varying_density():
+    """Circularly polarised Alfven wave with rho0 != 1: u_perp = -b_perp / sqrt(rho0)
+    and B = B0 e_axis + b_perp, so u.B = -b0^2 / sqrt(rho0) at every point (paper
+    Section V-B reads the cross term u.B).  Using m.B instead of u.B would give
+    -sqrt(rho0) b0^2, 2.25x larger in magnitude at rho0 = 2.25."""
+    rho0, b0 = 2.25, 0.4
+    _, d = _cp_wave_diag(rho0, b0)
+    assert abs(d["h_cross"] - (-b0 * b0 / math.sqrt(rho0))) < 1e-14
+    assert abs(d["h_cross"] - (-math.sqrt(rho0) * b0 * b0)) > 0.1
+
+
+def test_mach_numbers_closed_form():
+    """Section III: c_s = sqrt(gamma <P>/<rho>), V_A = <|B|>/sqrt(<rho>),
+    M_s = <|u|>/c_s, M_A = <|u|>/V_A.  On the CP wave |u| = b0/sqrt(rho0) and
+    |B| = sqrt(B0^2 + b0^2) at every point, P = P0 and rho = rho0."""
+    gamma, rho0, b0, B0, P0 = 5.0 / 3.0, 2.25, 0.4, 1.3, 0.7
+    _, d = _cp_wave_diag(rho0, b0, B0=B0, P0=P0)
+    cs = math.sqrt(gamma * P0 / rho0)
+    va = math.sqrt(B0 * B0 + b0 * b0) / math.sqrt(rho0)
+    uabs = b0 / math.sqrt(rho0)
+    assert abs(d["c_s"] - cs) < 1e-14
+    assert abs(d["v_a"] - va) < 1e-14
+    assert abs(d["mach_s"] - uabs / cs) < 1e-14
+    assert abs(d["mach_a"] - uabs / va) < 1e-14
+    # a <|m|> numerator (rho0 times larger) or a missing sqrt in V_A would miss
+    assert abs(d["mach_s"] - rho0 * uabs / cs) > 0.1 * uabs / cs
+    assert abs(d["v_a"] - math.sqrt(B0 * B0 + b0 * b0) / rho0) > 0.1 * va
+
+
+def test_cross_helicity_conserved_isentropic_ideal():
+    """Ideal MHD conserves <u.B> when the pressure is a function of density
+    alone; an isentropic start P = K rho^gamma stays isentropic while the flow is
+    smooth, so the only drift of the discrete run is the integrator's O(dt^2).
+    Halving dt must cut the drift about 4x (and H_M and E_tot stay put)."""
+    gamma, n, T = 5.0 / 3.0, 16, 0.06
+    z, y, x = I.grid(n)
+    rho = 1.0 + 0.2 * np.cos(x + y) + 0.1 * np.sin(z) + 0 * x
+    u = np.zeros((3, n, n, n))
+    u[0] = 0.4 * np.sin(y) + 0.2 * np.cos(z) + 0 * x
+    u[1] = 0.3 * np.sin(z) + 0.2 * np.cos(x) + 0 * y
+    u[2] = 0.3 * np.sin(x + y) + 0 * z
+    B = np.zeros((3, n, n, n))
+    B[0] = 0.5 * np.cos(y + z) + 0.2 + 0 * x
+    B[1] = 0.4 * np.sin(z) + 0.3 * np.cos(x) + 0 * y
+    B[2] = 0.3 * np.sin(x - y) + 0.1 + 0 * z
+    P = 1.5 * rho ** gamma
+    U0 = I.conserved(rho, u, B, P, gamma)
+    d0 = O.diag(U0, gamma)
+    assert abs(d0["h_cross"]) > 0.01
+    drift = []
+    for steps in (60, 120, 240):
+        U = O.run(U0, steps, T / steps, gamma)
+        d1 = O.diag(U, gamma)
+        assert abs(d1["e_tot"] - d0["e_tot"]) < 1e-12 * d0["e_tot"]
+        drift.append(abs(d1["h_cross"] - d0["h_cross"]))
+    r1, r2 = drift[0] / drift[1], drift[1] / drift[2]
+    assert 3.2 < r1 < 4.8 and 3.2 < r2 < 4.8, drift
