@@ -15,7 +15,12 @@
  *   - the spectral right-hand side R(U^) of the eight conserved fields
  *     (rho, m_x, m_y, m_z, B_x, B_y, B_z, E), Heaviside-Lorentz units
  *     (4*pi -> 1, c -> 1), ideal-gas closure P = (gamma-1)(E - m.u/2 - |B|^2/2);
- *   - second-order Adams-Bashforth stepping, Euler on the first step;
+ *   - second-order Adams-Bashforth stepping, Euler on the first step; the
+ *     classical Runge-Kutta 4 and a second-order Adams-Bashforth-Moulton
+ *     predictor-corrector (Section II names all three);
+ *   - the variants of Section V: viscous force nu lap u instead of the stress
+ *     form, the ABC body force rho f, and the kinematic mode (rho, m, E
+ *     frozen, B evolving);
  *   - FP64 volume-mean diagnostics with Neumaier compensated sums.
  *
  * Every function returns 0 on success and a negative value on a bad argument
@@ -32,13 +37,20 @@ extern "C" {
 
 #define ORC_NFIELDS 8
 
+/* Time integrators (orc_params.scheme) and options (orc_params.options). */
+enum { ORC_AB2 = 0, ORC_RK4 = 1, ORC_PC = 2 };
+enum { ORC_VISC_LAPLACIAN = 1, ORC_KINEMATIC = 2 };
+
 typedef struct {
     int32_t n;      /* grid points per side */
     double gamma;   /* ratio of specific heats */
-    double nu;      /* kinematic viscosity */
+    double nu;      /* kinematic viscosity (with ORC_VISC_LAPLACIAN: the coefficient of nu lap u) */
     double eta;     /* magnetic diffusivity */
     double dt;      /* fixed time step */
     double cfl;     /* Courant number used by the dt_cfl diagnostic */
+    int32_t scheme; /* ORC_AB2, ORC_RK4 or ORC_PC (orc_run) */
+    int32_t options;/* ORC_VISC_LAPLACIAN, ORC_KINEMATIC */
+    double force;   /* amplitude of the ABC body force (0 = unforced) */
 } orc_params;
 
 /* Indices of the diagnostic vector written by orc_diag. */
@@ -65,8 +77,9 @@ int orc_project(int32_t n, double* f);
 /* Real-space right-hand side: U[8][n^3] -> R[8][n^3], with U^ = D F U first. */
 int orc_rhs(const orc_params* p, const double* U, double* R);
 
-/* Advance U[8][n^3] in place by nsteps AB2 steps (Euler first), starting from
- * U^ = D F U.  On return U holds F^-1 of the final spectral state. */
+/* Advance U[8][n^3] in place by nsteps steps of p->scheme (AB2 and PC start
+ * with an Euler predictor), starting from U^ = D F U.  On return U holds
+ * F^-1 of the final spectral state. */
 int orc_run(const orc_params* p, double* U, int32_t nsteps);
 
 /* Diagnostics of the state U^ = D F U (see the ORC_* indices). */

@@ -26,6 +26,11 @@ DIAG_NAMES = (
 )
 
 
+# time integrators and options (oracle.h)
+SCHEMES = {"ab2": 0, "rk4": 1, "pc": 2}
+VISC_LAPLACIAN, KINEMATIC = 1, 2
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32),
@@ -34,6 +39,9 @@ class _Params(ctypes.Structure):
         ("eta", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("cfl", ctypes.c_double),
+        ("scheme", ctypes.c_int32),
+        ("options", ctypes.c_int32),
+        ("force", ctypes.c_double),
     ]
 
 
@@ -74,8 +82,10 @@ def _check(rc: int, what: str):
         raise RuntimeError(f"oracle {what} failed with status {rc}")
 
 
-def _params(n, gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=0.0, cfl=0.1) -> _Params:
-    return _Params(int(n), float(gamma), float(nu), float(eta), float(dt), float(cfl))
+def _params(n, gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=0.0, cfl=0.1, scheme="ab2", options=0,
+            force=0.0) -> _Params:
+    return _Params(int(n), float(gamma), float(nu), float(eta), float(dt), float(cfl), SCHEMES[scheme],
+                   int(options), float(force))
 
 
 def fft1d(x, sign: int = -1) -> np.ndarray:
@@ -105,17 +115,20 @@ def _fields(U) -> np.ndarray:
     return U
 
 
-def rhs(U, gamma=5.0 / 3.0, nu=0.0, eta=0.0) -> np.ndarray:
+def rhs(U, gamma=5.0 / 3.0, nu=0.0, eta=0.0, options=0, force=0.0) -> np.ndarray:
+    """options: VISC_LAPLACIAN | KINEMATIC; force: ABC body-force amplitude."""
     U = _fields(U)
     R = np.empty_like(U)
-    p = _params(U.shape[1], gamma, nu, eta)
+    p = _params(U.shape[1], gamma, nu, eta, options=options, force=force)
     _check(lib().orc_rhs(ctypes.byref(p), _ptr(U), _ptr(R)), "rhs")
     return R
 
 
-def run(U, nsteps: int, dt: float, gamma=5.0 / 3.0, nu=0.0, eta=0.0) -> np.ndarray:
+def run(U, nsteps: int, dt: float, gamma=5.0 / 3.0, nu=0.0, eta=0.0, scheme="ab2", options=0,
+        force=0.0) -> np.ndarray:
+    """scheme: "ab2", "rk4" or "pc" (AB2 predictor, trapezoidal corrector)."""
     U = _fields(U)
-    p = _params(U.shape[1], gamma, nu, eta, dt)
+    p = _params(U.shape[1], gamma, nu, eta, dt, scheme=scheme, options=options, force=force)
     _check(lib().orc_run(ctypes.byref(p), _ptr(U), int(nsteps)), "run")
     return U
 

@@ -123,6 +123,10 @@ typedef struct {
     int n;
     long n3;
     double gamma, nu, eta, dt, cfl;
+    int scheme;      /* ORC_AB2, ORC_RK4, ORC_PC */
+    int visc_lap;    /* 1: viscous force nu lap u (Section V) instead of div(2 nu rho S) */
+    int kinematic;   /* 1: rho, m, E frozen; only the induction equation evolves */
+    double force;    /* amplitude of the ABC body force rho f (Section V-B), 0 = none */
 } grid;
 
 /* Integer wavenumber of DFT index i on a box of length 2*pi. */
@@ -189,7 +193,7 @@ static void accum_ik(const grid* g, const cplx* in, int axis, double c, cplx* ac
 
 int orc_project(int32_t n, double* f) {
     if (n < 1 || !f) return -1;
-    grid g = {n, (long)n * n * n, 0, 0, 0, 0, 0};
+    grid g = {n, (long)n * n * n, 0, 0, 0, 0, 0, ORC_AB2, 0, 0, 0.0};
     cplx* a = (cplx*)xmalloc((size_t)g.n3 * sizeof(cplx));
     cplx* t = (cplx*)xmalloc((size_t)g.n3 * sizeof(cplx));
     int err = (!a || !t) ? -2 : 0;
@@ -258,6 +262,9 @@ static int add_divergence_term(const grid* g, rhs_work* w, int axis, double c, c
 static int rhs_spectral(const grid* g, const cplx* const* Uh, cplx* const* Rh, rhs_work* w) {
     const long n3 = g->n3;
     const double gm1 = g->gamma - 1.0, nu = g->nu, eta = g->eta;
+    /* coefficient of the stress form div(2 nu rho S) (Eqs. MHD2-MHD3); zero
+     * when the viscous force is nu lap u instead (added below) */
+    const double nu_s = g->visc_lap ? 0.0 : 2.0 * nu;
     int err = 0;
 
     /* (i) the state in real space */
@@ -315,7 +322,7 @@ static int rhs_spectral(const grid* g, const cplx* const* Uh, cplx* const* Rh, r
                 double P = gm1 * (E[p] - 0.5 * mu - 0.5 * B2);
                 double Ptot = P + 0.5 * B2;
                 w->flux[p] = m[i][p] * w->u[j][p] + (i == j ? Ptot : 0.0) - B[i][p] * B[j][p] -
-                             2.0 * nu * rho[p] * w->S[3 * i + j][p];
+                             nu_s * rho[p] * w->S[3 * i + j][p];
             }
             err = add_divergence_term(g, w, j, -1.0, Rh[F_MX + i]);
         }
@@ -333,7 +340,7 @@ static int rhs_spectral(const grid* g, const cplx* const* Uh, cplx* const* Rh, r
             double uB = u0 * B[0][p] + u1 * B[1][p] + u2 * B[2][p];
             double uS = u0 * w->S[0 * 3 + j][p] + u1 * w->S[1 * 3 + j][p] + u2 * w->S[2 * 3 + j][p];
             double BxJ = B[a][p] * w->J[b][p] - B[b][p] * w->J[a][p];
-            w->flux[p] = (E[p] + Ptot) * w->u[j][p] - uB * B[j][p] - 2.0 * nu * rho[p] * uS - eta * BxJ;
+            w->flux[p] = (E[p] + Ptot) * w->u[j][p] - uB * B[j][p] - nu_s * rho[p] * uS - eta * BxJ;
         }
         err = add_divergence_term(g, w, j, -1.0, Rh[F_E]);
     }
@@ -360,6 +367,61 @@ static int rhs_spectral(const grid* g, const cplx* const* Uh, cplx* const* Rh, r
                         Rh[F_BX + i][id] -= eta * (kx * kx + ky * ky + kz * kz) * Uh[F_BX + i][id];
                 }
     }
+
+    /* Viscous force nu lap u (the momentum equation of Section V) in place of
+     * the stress form: R_m += -nu |k|^2 u^.  Its work plus the viscous heating
+     * is nu lap(|u|^2/2), so R_E += -nu |k|^2 D F[|u|^2/2] keeps <E> conserved. */
+    if (g->visc_lap && !err) {
+        for (long p = 0; p < n3; ++p)
+            w->flux[p] = 0.5 * (w->u[0][p] * w->u[0][p] + w->u[1][p] * w->u[1][p] + w->u[2][p] * w->u[2][p]);
+        err = forward(g, w->flux, w->c0);
+        apply_mask(g, w->c0);
+        const int n = g->n;
+        for (int iz = 0; iz < n; ++iz)
+            for (int iy = 0; iy < n; ++iy)
+                for (int ix = 0; ix < n; ++ix) {
+                    double kx = wavenumber(ix, n), ky = wavenumber(iy, n), kz = wavenumber(iz, n);
+                    double k2 = kx * kx + ky * ky + kz * kz;
+                    long id = ((long)iz * n + iy) * n + ix;
+                    for (int i = 0; i < 3; ++i) Rh[F_MX + i][id] -= nu * k2 * w->uh[i][id];
+                    Rh[F_E][id] -= nu * k2 * w->c0[id];
+                }
+    }
+
+    /* ABC body force (Section V-B) with A = B = C = 1, k_f = 1, amplitude F0:
+     * f = F0 (sin z + cos y, sin x + cos z, sin y + cos x).  Momentum gains
+     * rho f, the total energy the work rho f.u = m.f; both dealiased. */
+    if (g->force != 0.0 && !err) {
+        const int n = g->n;
+        double* fx = (double*)xmalloc((size_t)n3 * sizeof(double));
+        if (!fx) return -2;
+        for (int c = 0; c < 3 && !err; ++c) {
+            for (int iz = 0; iz < n; ++iz)
+                for (int iy = 0; iy < n; ++iy)
+                    for (int ix = 0; ix < n; ++ix) {
+                        double x = TWO_PI * ix / n, y = TWO_PI * iy / n, z = TWO_PI * iz / n;
+                        double f = c == 0 ? sin(z) + cos(y) : (c == 1 ? sin(x) + cos(z) : sin(y) + cos(x));
+                        fx[((long)iz * n + iy) * n + ix] = g->force * f;
+                    }
+            for (long p = 0; p < n3; ++p) w->flux[p] = rho[p] * fx[p];
+            err = forward(g, w->flux, w->c0);
+            apply_mask(g, w->c0);
+            for (long p = 0; p < n3; ++p) Rh[F_MX + c][p] += w->c0[p];
+            for (long p = 0; p < n3 && !err; ++p) w->flux[p] = m[c][p] * fx[p];
+            if (!err) err = forward(g, w->flux, w->c0);
+            apply_mask(g, w->c0);
+            for (long p = 0; p < n3; ++p) Rh[F_E][p] += w->c0[p];
+        }
+        free(fx);
+    }
+
+    /* Kinematic mode (Section V-B, the dynamo runs with the density and
+     * velocity equations turned off): only B evolves, under the given flow. */
+    if (g->kinematic) {
+        memset(Rh[F_RHO], 0, (size_t)n3 * sizeof(cplx));
+        for (int i = 0; i < 3; ++i) memset(Rh[F_MX + i], 0, (size_t)n3 * sizeof(cplx));
+        memset(Rh[F_E], 0, (size_t)n3 * sizeof(cplx));
+    }
     return err;
 }
 
@@ -368,6 +430,11 @@ static int make_grid(const orc_params* p, grid* g) {
     g->n = p->n;
     g->n3 = (long)p->n * p->n * p->n;
     g->gamma = p->gamma; g->nu = p->nu; g->eta = p->eta; g->dt = p->dt; g->cfl = p->cfl;
+    if (p->scheme < ORC_AB2 || p->scheme > ORC_PC) return -1;
+    g->scheme = p->scheme;
+    g->visc_lap = (p->options & ORC_VISC_LAPLACIAN) != 0;
+    g->kinematic = (p->options & ORC_KINEMATIC) != 0;
+    g->force = p->force;
     return 0;
 }
 
@@ -416,30 +483,77 @@ int orc_rhs(const orc_params* p, const double* U, double* R) {
     return err;
 }
 
-/* Second-order Adams-Bashforth with a fixed step; the first step is Euler
- * (the history R^{-1} is taken equal to R^0). */
+/* Time integrators with a fixed step (Section II lists Adams-Bashforth,
+ * Runge-Kutta 4 and predictor-corrector and finds that they agree):
+ *   ORC_AB2: U^{n+1} = U^n + dt (3/2 R^n - 1/2 R^{n-1}); the first step is
+ *            Euler (the history R^{-1} is taken equal to R^0);
+ *   ORC_RK4: the classical four-stage Runge-Kutta scheme;
+ *   ORC_PC:  Adams-Bashforth-Moulton of second order: the AB2 step above as
+ *            predictor U*, then the trapezoidal corrector
+ *            U^{n+1} = U^n + dt/2 (R^n + R(U*)), history R^{n-1} <- R^n. */
 int orc_run(const orc_params* p, double* U, int32_t nsteps) {
     grid g;
     if (make_grid(p, &g) || !U || nsteps < 0) return -1;
+    const int scheme = g.scheme;
+    const int nsp = scheme == ORC_AB2 ? 3 : 5;
     cplx** Uh = alloc_spectra(&g, 8);
     cplx** Rh = alloc_spectra(&g, 8);
-    cplx** Rp = alloc_spectra(&g, 8);
+    cplx** Rp = alloc_spectra(&g, 8);                       /* history (AB2, PC) or stage sum (RK4) */
+    cplx** Us = nsp > 3 ? alloc_spectra(&g, 8) : NULL;      /* stage / predicted state */
+    cplx** Rs = nsp > 3 ? alloc_spectra(&g, 8) : NULL;      /* RHS of the stage state */
     rhs_work w;
-    int err = (!Uh || !Rh || !Rp) ? -2 : alloc_work(&g, &w);
+    int err = (!Uh || !Rh || !Rp || (nsp > 3 && (!Us || !Rs))) ? -2 : alloc_work(&g, &w);
+    const long n3 = g.n3;
+    const double dt = g.dt;
     if (!err) err = to_state(&g, U, Uh);
     for (int s = 0; s < nsteps && !err; ++s) {
         err = rhs_spectral(&g, (const cplx* const*)Uh, Rh, &w);
-        for (int f = 0; f < 8 && !err; ++f) {
-            if (s == 0) memcpy(Rp[f], Rh[f], (size_t)g.n3 * sizeof(cplx));
-            for (long q = 0; q < g.n3; ++q) {
-                Uh[f][q] += g.dt * (1.5 * Rh[f][q] - 0.5 * Rp[f][q]);
-                Rp[f][q] = Rh[f][q];
+        if (err) break;
+        if (scheme == ORC_AB2) {
+            for (int f = 0; f < 8; ++f) {
+                if (s == 0) memcpy(Rp[f], Rh[f], (size_t)n3 * sizeof(cplx));
+                for (long q = 0; q < n3; ++q) {
+                    Uh[f][q] += dt * (1.5 * Rh[f][q] - 0.5 * Rp[f][q]);
+                    Rp[f][q] = Rh[f][q];
+                }
             }
+        } else if (scheme == ORC_RK4) {
+            /* k1 = Rh; Rp accumulates k1 + 2 k2 + 2 k3 + k4 */
+            static const double c_stage[3] = {0.5, 0.5, 1.0}, w_stage[3] = {2.0, 2.0, 1.0};
+            for (int f = 0; f < 8; ++f)
+                for (long q = 0; q < n3; ++q) {
+                    Rp[f][q] = Rh[f][q];
+                    Us[f][q] = Uh[f][q] + c_stage[0] * dt * Rh[f][q];
+                }
+            for (int st = 0; st < 3 && !err; ++st) {
+                err = rhs_spectral(&g, (const cplx* const*)Us, Rs, &w);
+                for (int f = 0; f < 8 && !err; ++f)
+                    for (long q = 0; q < n3; ++q) {
+                        Rp[f][q] += w_stage[st] * Rs[f][q];
+                        if (st < 2) Us[f][q] = Uh[f][q] + c_stage[st + 1] * dt * Rs[f][q];
+                    }
+            }
+            for (int f = 0; f < 8 && !err; ++f)
+                for (long q = 0; q < n3; ++q) Uh[f][q] += dt / 6.0 * Rp[f][q];
+        } else {
+            /* predictor (AB2, Euler on the first step), then the trapezoidal corrector */
+            for (int f = 0; f < 8; ++f) {
+                if (s == 0) memcpy(Rp[f], Rh[f], (size_t)n3 * sizeof(cplx));
+                for (long q = 0; q < n3; ++q) Us[f][q] = Uh[f][q] + dt * (1.5 * Rh[f][q] - 0.5 * Rp[f][q]);
+            }
+            err = rhs_spectral(&g, (const cplx* const*)Us, Rs, &w);
+            for (int f = 0; f < 8 && !err; ++f)
+                for (long q = 0; q < n3; ++q) {
+                    Uh[f][q] += 0.5 * dt * (Rh[f][q] + Rs[f][q]);
+                    Rp[f][q] = Rh[f][q];
+                }
         }
     }
     for (int f = 0; f < 8 && !err; ++f) err = inverse(&g, Uh[f], w.c0, U + (long)f * g.n3);
-    if (Uh && Rh && Rp) free_work(&w);
+    if (Uh && Rh && Rp && (nsp == 3 || (Us && Rs))) free_work(&w);
     free_spectra(Uh, 8); free_spectra(Rh, 8); free_spectra(Rp, 8);
+    if (Us) free_spectra(Us, 8);
+    if (Rs) free_spectra(Rs, 8);
     return err;
 }
 
