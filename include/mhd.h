@@ -57,7 +57,7 @@ enum {
     MHD_E_HIP = -4,       /* a HIP runtime call failed (see mhd_last_error) */
     MHD_E_NONFINITE = -5, /* a non-finite value was found in the state */
     MHD_E_CFL = -6,       /* dt exceeded the CFL limit (only with MHD_FLAG_CHECK_CFL) */
-    MHD_E_STATE = -7      /* no state has been set yet */
+    MHD_E_STATE = -7      /* no state has been set yet, or a blob is not a valid checkpoint */
 };
 
 /* Working precision (mhd_params.precision) and real-field element types
@@ -71,19 +71,36 @@ enum { MHD_FP64 = 0, MHD_FP32 = 1, MHD_MIXED = 2 };
 
 /* mhd_params.flags */
 enum {
-    MHD_FLAG_CHECK_CFL = 1 /* mhd_diagnostics reports MHD_E_CFL when dt > dt_cfl seen by a step */
+    MHD_FLAG_CHECK_CFL = 1,      /* mhd_diagnostics reports MHD_E_CFL when dt > dt_cfl seen by a step */
+    MHD_FLAG_NO_GRAPH = 2,       /* mhd_step launches every kernel itself instead of replaying a HIP graph */
+    MHD_FLAG_VISC_LAPLACIAN = 4, /* viscous force nu lap u (Section V's momentum equation) instead of
+                                    div(2 nu rho S) (Eq. MHD2); the energy gains nu lap(|u|^2/2), its work
+                                    plus heating, so <E> stays conserved */
+    MHD_FLAG_KINEMATIC = 8       /* kinematic dynamo (Section V-B): rho, m and E are frozen and only the
+                                    induction equation evolves, under the frozen flow */
 };
+
+/* Time integrators (mhd_params.scheme); Section II names all three and finds
+ * that they agree.  MHD_AB2: U^{n+1} = U^n + dt (3/2 R^n - 1/2 R^{n-1}), Euler
+ * first (one right-hand side per step).  MHD_RK4: the classical four-stage
+ * Runge-Kutta scheme (four).  MHD_PC: the AB2 step as predictor U*, then the
+ * trapezoidal corrector U^{n+1} = U^n + dt/2 (R^n + R(U*)) (two). */
+enum { MHD_AB2 = 0, MHD_RK4 = 1, MHD_PC = 2 };
 
 typedef struct {
     int32_t n;         /* grid points per side */
     int32_t precision; /* MHD_FP64, MHD_FP32 or MHD_MIXED */
     int32_t flags;     /* MHD_FLAG_* */
-    int32_t reserved;  /* must be 0 */
+    int32_t scheme;    /* MHD_AB2 (0), MHD_RK4 or MHD_PC */
     double gamma;      /* ratio of specific heats, > 1 */
-    double nu;         /* kinematic viscosity, >= 0 (Eq. MHD2: div(2 nu rho S)) */
+    double nu;         /* kinematic viscosity, >= 0 (Eq. MHD2: div(2 nu rho S); with
+                          MHD_FLAG_VISC_LAPLACIAN the coefficient of nu lap u) */
     double eta;        /* magnetic diffusivity, >= 0 (Eq. MHD4: eta lap B) */
     double dt;         /* fixed time step, > 0 */
     double cfl;        /* Courant number of the dt_cfl diagnostic, > 0 (e.g. 0.1) */
+    double force;      /* amplitude F0 of the ABC body force rho f of Section V-B, f = F0 (sin z + cos y,
+                          sin x + cos z, sin y + cos x) (A = B = C = 1, k_f = 1): the momentum gains
+                          rho f and the energy its work m.f; 0 = unforced */
 } mhd_params;
 
 /* FP64 volume-mean diagnostics of the current state (Section III: dynamic
@@ -114,44 +131,88 @@ typedef struct {
 
 typedef struct mhd_ctx mhd_ctx;
 
-/* 1 if n is supported for `precision`, else 0. */
+/* 1 if n is supported for `precision`, else 0.  (Section II: the periodic
+ * box is discretised on n^3 points for the FFT; sizes are n = 2^a 3^b.) */
 int mhd_supported_size(int32_t n, int32_t precision);
 
 /* Bytes of device workspace mhd_init needs for these parameters, or 0 if the
  * parameters are invalid. */
 size_t mhd_workspace_bytes(const mhd_params* p);
 
-/* Creates a context.  d_workspace: caller-owned device memory of at least
- * mhd_workspace_bytes(p) bytes, 256-byte aligned.  hip_stream: the hipStream_t
- * every later call enqueues on (NULL = default stream).  Uploads the twiddle
- * tables (synchronously).  *out receives the context. */
+/* Creates a context for one run of Eqs. MHD1-MHD4 (Section III) with the
+ * transport coefficients nu, eta of Eqs. MHD2-MHD4 and the time step of the
+ * Adams-Bashforth scheme (Sections II and IV).  d_workspace: caller-owned
+ * device memory of at least mhd_workspace_bytes(p) bytes, 256-byte aligned
+ * (MHD_E_WORKSPACE otherwise).  hip_stream: the hipStream_t every later call
+ * enqueues on (NULL = default stream).  Uploads the twiddle tables
+ * (synchronously).  *out receives the context; MHD_E_ARG / MHD_E_SIZE for
+ * invalid parameters. */
 int mhd_init(const mhd_params* p, void* d_workspace, size_t ws_bytes, void* hip_stream, mhd_ctx** out);
 
 /* Sets the state to D F[U] for the real fields U = d_fields ([8][n][n][n],
- * element type dtype), resets t, the step count and the AB2 history (the next
- * step is an Euler step).  Inputs are rounded to the working precision. */
+ * element type dtype; caller-owned, read only) -- the spectral representation
+ * of the conserved variables of Eqs. MHD1-MHD4 that the pseudo-spectral method
+ * of Section II evolves -- and resets t, the step count and the AB2 history
+ * (the next step is an Euler step).  Inputs are rounded to the working
+ * precision.  MHD_E_ARG for a null pointer or a bad dtype. */
 int mhd_set_state(mhd_ctx* ctx, const void* d_fields, int32_t dtype);
 
-/* Writes F^-1 of the state to d_fields ([8][n][n][n], element type dtype). */
+/* Writes F^-1 of the state (the conserved fields of Eqs. MHD1-MHD4 on the
+ * grid, Section II's inverse transform) to the caller-owned d_fields
+ * ([8][n][n][n], element type dtype).  MHD_E_STATE if no state is set. */
 int mhd_get_state(mhd_ctx* ctx, void* d_fields, int32_t dtype);
 
-/* Pure right-hand side (Eqs. MHD1-MHD4): d_rhs_out = F^-1 R(D F[U]) for the
- * real fields U = d_fields_in; the context's state and history are untouched.
- * Both arrays [8][n][n][n] of element type dtype; they may not overlap. */
+/* Pure right-hand side (Eqs. MHD1-MHD4 of Section III, evaluated by the
+ * pseudo-spectral method of Section II): d_rhs_out = F^-1 R(D F[U]) for the
+ * real fields U = d_fields_in; the context's state, history and status are
+ * untouched.  Both arrays caller-owned, [8][n][n][n] of element type dtype;
+ * they may not overlap.  MHD_E_ARG for a null pointer or a bad dtype. */
 int mhd_rhs(mhd_ctx* ctx, const void* d_fields_in, void* d_rhs_out, int32_t dtype);
 
-/* Advances the state by nsteps >= 0 AB2 steps of the fixed dt
- * (U^{n+1} = U^n + dt (3/2 R^n - 1/2 R^{n-1}); the first step after
- * mhd_set_state is Euler).  Returns MHD_E_STATE if no state is set. */
+/* Advances the state by nsteps >= 0 steps of the Adams-Bashforth scheme
+ * (Sections II and IV; second order, fixed dt):
+ * U^{n+1} = U^n + dt (3/2 R^n - 1/2 R^{n-1}); the first step after
+ * mhd_set_state is Euler.  The first call launches the steady step's
+ * kernels once under stream capture and every later step replays that HIP
+ * graph (unless MHD_FLAG_NO_GRAPH is set or mhd_profile is recording); the
+ * arithmetic is the same either way.  Returns MHD_E_STATE if no state is
+ * set, MHD_E_ARG for nsteps < 0. */
 int mhd_step(mhd_ctx* ctx, int32_t nsteps);
 
-/* Computes the diagnostics of the current state into *h_out (host memory)
- * and synchronises the stream.  Returns MHD_E_NONFINITE if the state holds a
- * non-finite value, MHD_E_CFL if MHD_FLAG_CHECK_CFL is set and some step since
- * mhd_set_state ran with dt above its CFL limit; *h_out is filled either way. */
+/* Computes the diagnostics of the current state (Section III: c_s, V_A,
+ * M_s, M_A; Section V: energies per grid point, cross and magnetic helicity)
+ * into *h_out (host memory), with FP64 compensated (Neumaier) reductions, and
+ * synchronises the stream.  Returns MHD_E_NONFINITE if the state holds a
+ * non-finite value or a step met one, MHD_E_CFL if MHD_FLAG_CHECK_CFL is set
+ * and some step since mhd_set_state ran with dt above its CFL limit (the
+ * steps' largest signal speed is kept and reduced in FP64); *h_out is filled
+ * either way.  MHD_E_STATE if no state is set. */
 int mhd_diagnostics(mhd_ctx* ctx, mhd_diag* h_out);
 
-/* Test hook with the transform conventions above.  dir = -1: d_in is one real
+/* Checkpoint/restart of the multistep state.  The AB2 scheme (Sections II
+ * and IV) carries the previous right-hand side R^{n-1} besides U^n, so a
+ * restart needs both: a checkpoint blob holds a 256-byte header (format
+ * version, n, precision, step, t, dt, sizes and a 64-bit checksum of every
+ * other word), the compact state U^n, the history R^{n-1} and the CFL /
+ * non-finite status of the steps taken so far.  The blob is caller-owned
+ * device memory of mhd_checkpoint_bytes(ctx) bytes, 256-byte aligned.
+ *
+ * mhd_checkpoint_bytes: blob size for this context (0 for a null context).
+ * mhd_save: enqueues the copy and the checksum on the context's stream
+ *   (asynchronous); MHD_E_STATE if no state is set, MHD_E_ARG for a null or
+ *   misaligned blob.
+ * mhd_load: synchronises the stream, checks the header and the checksum and,
+ *   if they hold, enqueues the copies into the context: a run continued from
+ *   a blob is bit for bit the run that saved it.  MHD_E_STATE for a blob that
+ *   is not a valid checkpoint (wrong format or size, checksum mismatch: the
+ *   context is left unchanged); MHD_E_ARG for a valid checkpoint of a
+ *   different n, precision or dt. */
+size_t mhd_checkpoint_bytes(const mhd_ctx* ctx);
+int mhd_save(mhd_ctx* ctx, void* d_blob);
+int mhd_load(mhd_ctx* ctx, const void* d_blob);
+
+/* Test hook with the transform conventions above (Section II: the forward
+ * and inverse FFTs of the pseudo-spectral method).  dir = -1: d_in is one real
  * n^3 field, d_out its compact spectrum D F[f].  dir = +1: d_in a compact
  * spectrum, d_out the real field F^-1 (n^-3 normalised).  Both in the working
  * precision; the arrays may not overlap.  Uses the context's workspace. */
@@ -194,6 +255,13 @@ int mhd_profile_read(mhd_ctx* ctx, double* ms, int64_t* launches, double* bytes,
  * launches, each array read or written once), or 0 for a null context. */
 double mhd_step_bytes(const mhd_ctx* ctx);
 
+/* Benchmark hook (not physics): enqueues one streaming copy of `bytes`
+ * (a multiple of 16; both pointers 16-byte aligned, caller-owned device
+ * memory) from d_src to d_dst on hip_stream, with the library's own copy
+ * kernel.  Its rate is the practical HBM ceiling the passes are compared
+ * with.  MHD_E_ARG for bad sizes or alignment. */
+int mhd_bench_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream);
+
 /* Releases the host-side context (not the caller's workspace). */
 int mhd_destroy(mhd_ctx* ctx);
 
@@ -214,7 +282,9 @@ const char* mhd_last_error(const mhd_ctx* ctx);
  * a single context with the same parameters, so a member's state matches a
  * solo run bit for bit, and a non-finite value in one member never reaches
  * another.  The paper runs one simulation at a time; the ensemble is an
- * extension of the same per-step operator. */
+ * extension of the same per-step operator.  Members use the AB2 scheme
+ * without the Section V variants (scheme MHD_AB2, no force, neither
+ * MHD_FLAG_VISC_LAPLACIAN nor MHD_FLAG_KINEMATIC; MHD_E_ARG otherwise). */
 typedef struct mhd_ens mhd_ens;
 
 /* Bytes of device workspace for the members p[0..count-1] (count >= 1), or 0

@@ -91,6 +91,9 @@ double orc_neumaier_sum(const double* x, int64_t n);
 /* Number of OpenMP threads the oracle uses (1 if built without OpenMP). */
 int32_t orc_num_threads(void);
 
+/* Sets the number of OpenMP threads of later calls (threads > 0). */
+void orc_set_num_threads(int32_t threads);
+
 #ifdef __cplusplus
 }
 #endif

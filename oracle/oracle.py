@@ -67,6 +67,8 @@ def lib():
         L.orc_neumaier_sum.argtypes = [dp, ctypes.c_int64]
         L.orc_neumaier_sum.restype = ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int32
+        L.orc_set_num_threads.argtypes = [ctypes.c_int32]
+        L.orc_set_num_threads.restype = None
         for name in ("orc_fft1d", "orc_fft3d", "orc_project", "orc_rhs", "orc_run", "orc_diag"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -148,3 +150,7 @@ def neumaier_sum(x) -> float:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(threads: int) -> None:
+    lib().orc_set_num_threads(int(threads))

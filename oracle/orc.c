@@ -692,3 +692,11 @@ int32_t orc_num_threads(void) {
     return 1;
 #endif
 }
+
+void orc_set_num_threads(int32_t threads) {
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}

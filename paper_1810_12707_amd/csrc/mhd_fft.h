@@ -974,8 +974,14 @@ __device__ __forceinline__ void fft_reg(cx<T>* buf, const cx<T>* tw, int tid, in
 // items are split into eight contiguous ranges, one per XCD, and the
 // workgroups resident on an XCD (ids w with w mod 8 = x) walk that XCD's
 // range together.  Returns the k-th item of workgroup w, or -1 when done.
-__device__ __forceinline__ int64_t xcd_item(int w, int G, int64_t k, int64_t total) {
+// A grid of fewer than eight workgroups leaves some XCDs without one, so it
+// walks the items with a plain stride instead.
+__host__ __device__ __forceinline__ int64_t xcd_item(int w, int G, int64_t k, int64_t total) {
   constexpr int X = 8;
+  if (G < X) {
+    const int64_t idx = (int64_t)w + k * G;
+    return idx < total ? idx : -1;
+  }
   const int xcd = w % X, slot = w / X;
   const int per = G / X + (xcd < G % X ? 1 : 0);
   const int64_t base = total / X, rem = total % X;

@@ -117,8 +117,8 @@ __global__ void __launch_bounds__(kThreads) k_rho_rhs(const RhsArgs<T> a) {
   const T dx = T(kx) * mx.x + T(ky) * my.x + T(kz) * mz.x;
   const T dy = T(kx) * mx.y + T(ky) * my.y + T(kz) * mz.y;
   V2 R;
-  R.x = dy;  // -i (dx + i dy)
-  R.y = -dx;
+  R.x = a.kinematic ? T(0) : dy;  // -i (dx + i dy); zero with the density frozen
+  R.y = a.kinematic ? T(0) : -dx;
   if (a.rout) {
     reinterpret_cast<V2*>(member_ptr(a.rout, mem, ms))[idx] = R;
     return;
@@ -136,6 +136,117 @@ __global__ void __launch_bounds__(kThreads) k_rho_rhs(const RhsArgs<T> a) {
   u.y += dt * ii;
   state[idx] = u;
   rprev[idx] = R;
+}
+
+// ABC body force of Section V-B in spectral form.  With f = F0 (sin z + cos y,
+// sin x + cos z, sin y + cos x), the product of a band-limited field g with
+// one term is a shift of its spectrum: F[g sin z](k) = (g^(k - e_z) -
+// g^(k + e_z)) / 2i, F[g cos y](k) = (g^(k - e_y) + g^(k + e_y)) / 2.  The
+// products have modes up to K + 1 < n/2, so this is exactly the dealiased
+// pseudo-spectral product D F[g f].  Writes force [4][sc]: D F[rho f_x],
+// D F[rho f_y], D F[rho f_z] and the work D F[m.f].  One thread per compact
+// entry; kx < 0 neighbours come from Hermitian symmetry, out-of-band ones are
+// zero.  Reads the state before anything of this step overwrites it.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_force_abc(const T* __restrict__ state, T* __restrict__ force, Geo g,
+                                                       double f0) {
+  using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int64_t plane = (int64_t)g.nb * g.nhp;
+  const int lz = (int)(idx / plane);
+  const int rem = (int)(idx - (int64_t)lz * plane);
+  const int ly = rem / g.nhp, kx = rem - ly * g.nhp;
+  if (idx >= g.sc || kx >= g.nh) return;
+  const int kz = lz <= g.K ? lz : lz - g.nb;
+  const int ky = ly <= g.K ? ly : ly - g.nb;
+  const V2* S = reinterpret_cast<const V2*>(state);
+  // spectrum of state field fld at (qx, qy, qz), any signs
+  auto at = [&](int fld, int qx, int qy, int qz) -> V2 {
+    V2 z;
+    z.x = T(0);
+    z.y = T(0);
+    bool conj = false;
+    if (qx < 0) {
+      qx = -qx;
+      qy = -qy;
+      qz = -qz;
+      conj = true;
+    }
+    if (qx > g.K || qy > g.K || qy < -g.K || qz > g.K || qz < -g.K) return z;
+    const int by = qy >= 0 ? qy : qy + g.nb, bz = qz >= 0 ? qz : qz + g.nb;
+    z = S[fld * g.sc + ((int64_t)bz * g.nb + by) * g.nhp + qx];
+    if (conj) z.y = -z.y;
+    return z;
+  };
+  // (g^(k - e) - g^(k + e)) / 2i and (g^(k - e) + g^(k + e)) / 2 along axis e
+  auto sin_term = [&](int fld, int ax) -> V2 {
+    const int dx = ax == 0, dy = ax == 1, dz = ax == 2;
+    const V2 m = at(fld, kx - dx, ky - dy, kz - dz), p = at(fld, kx + dx, ky + dy, kz + dz);
+    V2 r;
+    r.x = T(0.5) * (m.y - p.y);  // (a) / 2i = -i a / 2
+    r.y = T(-0.5) * (m.x - p.x);
+    return r;
+  };
+  auto cos_term = [&](int fld, int ax) -> V2 {
+    const int dx = ax == 0, dy = ax == 1, dz = ax == 2;
+    const V2 m = at(fld, kx - dx, ky - dy, kz - dz), p = at(fld, kx + dx, ky + dy, kz + dz);
+    V2 r;
+    r.x = T(0.5) * (m.x + p.x);
+    r.y = T(0.5) * (m.y + p.y);
+    return r;
+  };
+  // f_x = sin z + cos y, f_y = sin x + cos z, f_z = sin y + cos x
+  const int s_ax[3] = {2, 0, 1}, c_ax[3] = {1, 2, 0};
+  V2* F = reinterpret_cast<V2*>(force);
+  V2 work;
+  work.x = T(0);
+  work.y = T(0);
+  const T a = T(f0);
+  for (int c = 0; c < 3; ++c) {
+    const V2 s1 = sin_term(0, s_ax[c]), c1 = cos_term(0, c_ax[c]);
+    V2 v;
+    v.x = a * (s1.x + c1.x);
+    v.y = a * (s1.y + c1.y);
+    F[c * g.sc + idx] = v;
+    const V2 s2 = sin_term(1 + c, s_ax[c]), c2 = cos_term(1 + c, c_ax[c]);
+    work.x += a * (s2.x + c2.x);
+    work.y += a * (s2.y + c2.y);
+  }
+  F[3 * g.sc + idx] = work;
+}
+
+// Stage arithmetic of the Runge-Kutta and predictor-corrector schemes over the
+// eight compact fields (one thread per entry, padding skipped):
+//   CB_RK_FIRST:  acc = R;          us = u + c R
+//   CB_RK_MID:    acc += w R;       us = u + c R
+//   CB_RK_LAST:   u += c (acc + R)
+//   CB_PC_PRED:   us = u + dt (a_cur R + a_prev acc); acc = R   (acc = history)
+//   CB_PC_CORR:   u += c (acc + R)                              (acc = R^n)
+enum { CB_RK_FIRST = 0, CB_RK_MID, CB_RK_LAST, CB_PC_PRED, CB_PC_CORR };
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_combine(T* __restrict__ u, const T* __restrict__ R,
+                                                     T* __restrict__ acc, T* __restrict__ us, Geo g, int op,
+                                                     double c, double w, double a_cur, double a_prev) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // entry of the 8 fields
+  if (e >= 8 * g.sc) return;
+  const int64_t idx = e % g.sc;
+  if (idx % g.nhp >= g.nh) return;  // kx padding: never read or written
+  const int64_t j = 2 * e;
+  for (int h = 0; h < 2; ++h) {
+    const T r = R[j + h];
+    switch (op) {
+      case CB_RK_FIRST: acc[j + h] = r; us[j + h] = u[j + h] + T(c) * r; break;
+      case CB_RK_MID: acc[j + h] += T(w) * r; us[j + h] = u[j + h] + T(c) * r; break;
+      case CB_PC_PRED: {
+        // the Euler start (a_prev = 0) never reads the history, which may not exist yet
+        const T hist = a_prev != 0.0 ? T(a_prev) * acc[j + h] : T(0);
+        us[j + h] = u[j + h] + T(c) * (T(a_cur) * r + hist);
+        acc[j + h] = r;
+        break;
+      }
+      default: u[j + h] += T(c) * (acc[j + h] + r); break;  // CB_RK_LAST, CB_PC_CORR
+    }
+  }
 }
 
 template <typename T>
@@ -181,9 +292,78 @@ k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restr
   }
 }
 
+// Streaming copy of n 16-byte words (the benchmark's practical HBM
+// ceiling): a grid-stride loop with four independent 16-byte loads in flight
+// per thread before their stores.
+__global__ void __launch_bounds__(kThreads) k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                         int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// Checkpoint blob header (256 bytes at the start of the blob).
+struct CkptHeader {
+  char magic[8];           // "MHDCKPT"
+  uint32_t version;        // kCkptVersion
+  int32_t n, precision;    // grid and working precision of the saving context
+  int32_t first_step;      // 1: the next step is the Euler start (no history yet)
+  int64_t step;            // steps since the state was set
+  double t, dt;            // simulated time; the fixed step of the AB2 history
+  uint64_t payload_bytes;  // bytes after the header
+  uint64_t sc;             // complex values per compact spectrum
+  uint64_t pad[23];
+  uint64_t checksum;       // hash of every other word of the blob
+};
+static_assert(sizeof(CkptHeader) == 256, "checkpoint header is 256 bytes");
+constexpr uint32_t kCkptVersion = 1;
+constexpr int kCkptSumWord = 31;  // index of `checksum` among the header's 64-bit words
+
+// Writes the header (passed by value, so the launch captures it) to dst.
+__global__ void k_write_header(CkptHeader h, CkptHeader* dst) {
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(&h);
+  uint64_t* d = reinterpret_cast<uint64_t*>(dst);
+  const int i = threadIdx.x;
+  if (i < 32) d[i] = i == kCkptSumWord ? 0ull : src[i];
+}
+
+// Order-independent 64-bit hash of words[0..nwords) with word `skip` taken as
+// zero: the sum (mod 2^64) of the SplitMix64 finaliser applied to each word
+// offset by its index, so a changed word or two swapped words change it.
+// Block sums are added into *out with one atomic per block (addition mod 2^64
+// commutes, so the result does not depend on block order).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void __launch_bounds__(kThreads)
+k_blob_hash(const uint64_t* __restrict__ words, int64_t nwords, int64_t skip, unsigned long long* out) {
+  __shared__ uint64_t s[kThreads];
+  uint64_t acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * kThreads) {
+    const uint64_t w = i == skip ? 0ull : words[i];
+    acc += mix64(w + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull);
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, (unsigned long long)s[0]);
 }
 
 }  // namespace mhd
@@ -194,9 +374,9 @@ using namespace mhd;
 
 namespace {
 
-constexpr int kStatusWords = 4;  // u32: [0] max CFL speed seen by steps (float bits), [1] non-finite count,
-                                 // [2..3] the same for pure RHS evaluations (not reported)
-constexpr int kResWords = 32;    // reduced diagnostics
+constexpr int kResWords = 32;    // reduced diagnostics: [0, kDiagQ) real-space, [16, 16 + kSpecQ) spectral,
+                                 // [24] max signal speed seen by steps, [25] their non-finite count
+constexpr int kResStatus = 24;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -226,7 +406,7 @@ Geo make_geo(int n) {
 }
 
 struct Layout {
-  size_t tw, state, rprev, uhat, tstate, trhs, iz, iy, part, spart, status, res, total;
+  size_t tw, state, rprev, uhat, tstate, trhs, force, iz, iy, part, spart, status, res, hash, total;
 };
 
 Layout make_layout(const Geo& g, size_t tsize) {
@@ -237,17 +417,19 @@ Layout make_layout(const Geo& g, size_t tsize) {
   L.tw = take((size_t)g.n * cplx);
   L.state = take(8 * (size_t)g.sc * cplx);
   L.rprev = take(8 * (size_t)g.sc * cplx);
-  L.uhat = take(3 * (size_t)g.sc * cplx);
+  L.uhat = take(4 * (size_t)g.sc * cplx);
   L.tstate = take(8 * (size_t)g.sc * cplx);
   L.trhs = take(8 * (size_t)g.sc * cplx);
+  L.force = take(4 * (size_t)g.sc * cplx);
   L.iz = take(12 * (size_t)g.iz * cplx);
   L.iy = take(16 * (size_t)g.iy * cplx);
   const size_t rows = (size_t)g.n * g.n / 2;
   const size_t spec_blocks = (size_t)((g.sc + kThreads - 1) / kThreads);
   L.part = take(rows * kDiagQ * sizeof(double));
   L.spart = take(spec_blocks * kSpecQ * sizeof(double));
-  L.status = take(kStatusWords * sizeof(double));
+  L.status = take((size_t)kStatusSlots * 2 * sizeof(double));
   L.res = take(kResWords * sizeof(double));
+  L.hash = take(sizeof(uint64_t));
   L.total = off;
   return L;
 }
@@ -277,6 +459,10 @@ struct mhd_ctx {
   std::vector<double> rec_bytes;
   int nrec = 0;
   int64_t dropped = 0;
+  // the steady AB2 step as a HIP graph (captured at the first graph step)
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -351,14 +537,14 @@ struct Engine {
   T* uhat() const { return at(c->L.uhat); }
   T* tstate() const { return at(c->L.tstate); }
   T* trhs() const { return at(c->L.trhs); }
+  T* force() const { return at(c->L.force); }
   T* tw() const { return at(c->L.tw); }
   T* iz(int slot) const { return at(c->L.iz) + 2 * (size_t)slot * g.iz; }
   T* iy(int slot) const { return at(c->L.iy) + 2 * (size_t)slot * g.iy; }
   T* spec_field(T* base, int f) const { return base + 2 * (size_t)f * g.sc; }
   double* part() const { return reinterpret_cast<double*>(c->ws + c->L.part); }
   double* spart() const { return reinterpret_cast<double*>(c->ws + c->L.spart); }
-  unsigned* status() const { return reinterpret_cast<unsigned*>(c->ws + c->L.status); }
-  unsigned* scratch_status() const { return status() + 2; }
+  double* status() const { return reinterpret_cast<double*>(c->ws + c->L.status); }
   double* res() const { return reinterpret_cast<double*>(c->ws + c->L.res); }
 
   // Algorithmic HBM bytes of one launch: each array read or written once,
@@ -368,18 +554,20 @@ struct Engine {
     return (n_sc * nb * nb * nh + n_iz * n * nb * nh + n_iy * n * n * nh) * 2.0 * sizeof(T);
   }
   double class_bytes(int cls) const {
+    const double a4 = (c->p.flags & MHD_FLAG_VISC_LAPLACIAN) ? 1 : 0;  // q = |u|^2/2 beside u
+    const double fo = c->p.force != 0.0 ? 4 : 0;                       // body-force spectra
     switch (cls) {
       case MHD_PASS_ZINV_A: return cbytes(4, 4, 0);
       case MHD_PASS_YINV_A: return cbytes(0, 4, 4);
-      case MHD_PASS_XA: return cbytes(0, 0, 7);
-      case MHD_PASS_YFWD_A: return cbytes(0, 3, 3);
-      case MHD_PASS_ZFWD_A: return cbytes(3, 3, 0);
+      case MHD_PASS_XA: return cbytes(0, 0, 7 + a4);
+      case MHD_PASS_YFWD_A: return cbytes(0, 3 + a4, 3 + a4);
+      case MHD_PASS_ZFWD_A: return cbytes(3 + a4, 3 + a4, 0);
       case MHD_PASS_ZINV_B: return cbytes(7, 12, 0);
       case MHD_PASS_YINV_B: return cbytes(0, 12, 12);
       case MHD_PASS_XB: return cbytes(0, 0, 28);
       case MHD_PASS_YFWD_B: return cbytes(0, 12, 12);
-      case MHD_PASS_ZRHS: return cbytes(28, 12, 0);
-      case MHD_PASS_RHO: return cbytes(7, 0, 0);
+      case MHD_PASS_ZRHS: return cbytes(28 + 4 * a4 + fo, 12, 0);
+      case MHD_PASS_RHO: return cbytes(7 + 2 * fo, 0, 0);
       case MHD_PASS_REDUCE: return 0.0;
       default: return 0.0;
     }
@@ -440,7 +628,8 @@ struct Engine {
     const bool inv = (kind == PK_ZINV || kind == PK_YINV);
     const int64_t items = (int64_t)(z ? ztiles() : g.n * ytiles()) * nout * ms.n;
     int64_t blocks = (int64_t)(c->col_blocks[inv ? (maxt > 1 ? 2 : 1) : 0] * ms.col_scale);
-    if (blocks < 1) blocks = 1;
+    // at least one workgroup per XCD range of the item walk (or one per item)
+    if (blocks < 8) blocks = 8;
     if (blocks > items) blocks = items;
     dim3 grid((unsigned)blocks);
     if (inv) k.col_inv(maxt, a, grid, c->stream);
@@ -479,6 +668,7 @@ struct Engine {
     const int64_t items = (int64_t)g.n * g.n / 2 * ms.n;
     if (blocks < 1) blocks = 1;
     if (blocks > items) blocks = items;
+    if (blocks > kStatusSlots) blocks = kStatusSlots;  // one status slot per flux-pass workgroup
     return dim3((unsigned)blocks);
   }
 
@@ -535,6 +725,9 @@ struct Engine {
     k.row(RM_XINV_REAL, r, row_grid(RM_XINV_REAL), c->stream);
   }
 
+  // Outputs of phase A: u^ (3), and q^ = D F[|u|^2/2] with the viscous-force variant.
+  int na() const { return (c->p.flags & MHD_FLAG_VISC_LAPLACIAN) ? 4 : 3; }
+
   // Phase A: u^ = D F[m / rho] from the state U.
   void phase_a(T* U) {
     const T* zi[4];
@@ -551,19 +744,24 @@ struct Engine {
     RowArgs<T> r = row_args();
     set_in(r, 0);
     set_out(r, 4);
+    r.nf = na();
     timed(MHD_PASS_XA, [&] { k.row(RM_XA, r, row_grid(RM_XA), c->stream); });
-    T* ui[3] = {iy(4), iy(5), iy(6)};
-    T* uo[3] = {iz(0), iz(1), iz(2)};
-    timed(MHD_PASS_YFWD_A, [&] { y_copy(PK_YFWD, 3, ui, uo); });
-    T* ho[3] = {spec_field(uhat(), 0), spec_field(uhat(), 1), spec_field(uhat(), 2)};
-    OutSpec cp[3] = {copy_spec(0, 1.0), copy_spec(1, 1.0), copy_spec(2, 1.0)};
-    timed(MHD_PASS_ZFWD_A, [&] { col(PK_ZFWD, 3, uo, 3, ho, cp); });
+    const int nu_ = na();
+    T* ui[4] = {iy(4), iy(5), iy(6), iy(7)};
+    T* uo[4] = {iz(0), iz(1), iz(2), iz(3)};
+    timed(MHD_PASS_YFWD_A, [&] { y_copy(PK_YFWD, nu_, ui, uo); });
+    T* ho[4] = {spec_field(uhat(), 0), spec_field(uhat(), 1), spec_field(uhat(), 2), spec_field(uhat(), 3)};
+    OutSpec cp[4] = {copy_spec(0, 1.0), copy_spec(1, 1.0), copy_spec(2, 1.0), copy_spec(3, 1.0)};
+    timed(MHD_PASS_ZFWD_A, [&] { col(PK_ZFWD, nu_, uo, nu_, ho, cp); });
   }
 
   // Phase B: fluxes and the spectral RHS of state U.  rout == nullptr: AB2
   // update of U and the history with the members' coefficients ms.a_cur,
-  // ms.a_prev.
-  void phase_b(T* U, T* rout) {
+  // ms.a_prev.  record_status: fold the flux pass's CFL speed and
+  // non-finite count into the status slots (steps do; pure right-hand sides
+  // and the later stages of a multistage step do not).
+  void phase_b(T* U, T* rout) { phase_b(U, rout, rout == nullptr); }
+  void phase_b(T* U, T* rout, bool record_status) {
     const double s = inv_n3();
     // inputs: 0-2 B^, 3 E^, 4-6 u^
     const T* zi[7] = {spec_field(U, 4), spec_field(U, 5), spec_field(U, 6), spec_field(U, 7),
@@ -592,9 +790,9 @@ struct Engine {
     RowArgs<T> r = row_args();
     set_in(r, 0);
     set_out(r, 0);
-    // the step's CFL speed and non-finite count fold into the status words; a
-    // pure RHS evaluation writes them to a scratch pair instead
-    r.status = rout ? scratch_status() : status();
+    if (c->p.flags & MHD_FLAG_VISC_LAPLACIAN)
+      for (int m = 0; m < ms.n; ++m) r.nu[m] = 0.0;  // no stress-form terms: the force is added spectrally
+    r.status = record_status ? status() : nullptr;
     timed(MHD_PASS_XB, [&] { k.row(RM_XB, r, row_grid(RM_XB), c->stream); });
     T* fi[12];
     T* fo[12];
@@ -622,6 +820,10 @@ struct Engine {
     q.rprev = rprev();
     q.rout = rout;
     q.tw = tw();
+    q.uhat = uhat();
+    q.mu = (c->p.flags & MHD_FLAG_VISC_LAPLACIAN) ? c->p.nu : 0.0;
+    q.kinematic = (c->p.flags & MHD_FLAG_KINEMATIC) ? 1 : 0;
+    q.force = c->p.force != 0.0 ? force() : nullptr;
     for (int m = 0; m < ms.n; ++m) {
       q.dt[m] = ms.dt[m];
       q.a_cur[m] = ms.a_cur[m];
@@ -632,6 +834,10 @@ struct Engine {
     q.bt = batch();
     const unsigned sblocks = (unsigned)((g.sc + kThreads - 1) / kThreads);
     timed(MHD_PASS_RHO, [&] {
+      // the body force reads rho^ and m^ of this step before either is updated
+      if (q.force)
+        hipLaunchKernelGGL((k_force_abc<T>), dim3(sblocks), dim3(kThreads), 0, c->stream, U, force(), g,
+                           c->p.force);
       hipLaunchKernelGGL((k_rho_rhs<T>), dim3(sblocks, (unsigned)ms.n), dim3(kThreads), 0, c->stream, q);
     });
     timed(MHD_PASS_ZRHS, [&] { k.rhs(q, dim3((unsigned)(rtiles() * 7 * ms.n)), c->stream); });
@@ -640,11 +846,57 @@ struct Engine {
   double step_bytes() const {
     double b = 0.0;
     for (int cls = 0; cls < MHD_PASS_COUNT; ++cls) b += class_bytes(cls);
-    return b;
+    const double evals = c->p.scheme == MHD_RK4 ? 4 : (c->p.scheme == MHD_PC ? 2 : 1);
+    // a multistage step: its right-hand sides plus the stage arithmetic over the 8-field sets
+    const double stage = c->p.scheme == MHD_RK4 ? 4 * cbytes(24, 0, 0) + cbytes(8, 0, 0)
+                                                 : (c->p.scheme == MHD_PC ? 2 * cbytes(24, 0, 0) : 0.0);
+    return b * evals + stage;
+  }
+
+  void combine(int op, double cc, double w, double a_cur = 0.0, double a_prev = 0.0) {
+    const unsigned blocks = (unsigned)((8 * g.sc + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL((k_combine<T>), dim3(blocks), dim3(kThreads), 0, c->stream, state(), trhs(), rprev(),
+                       tstate(), g, op, cc, w, a_cur, a_prev);
+  }
+
+  // One step of the context's scheme (single runs).  AB2: one right-hand
+  // side with the update fused into its last pass.  RK4 and PC: right-hand
+  // sides into trhs, stage states in tstate, and rprev as the RK4 stage sum
+  // or the PC history.  The flux pass of the first evaluation (the state at
+  // t_n) records the CFL / non-finite status.
+  void step_once(bool first) {
+    const double dt = c->p.dt;
+    if (c->p.scheme == MHD_RK4) {
+      phase_a(state());
+      phase_b(state(), trhs(), true);
+      combine(CB_RK_FIRST, 0.5 * dt, 0.0);
+      const double cs[3] = {0.5 * dt, dt, dt / 6.0};
+      for (int st = 0; st < 3; ++st) {
+        phase_a(tstate());
+        phase_b(tstate(), trhs(), false);
+        combine(st < 2 ? CB_RK_MID : CB_RK_LAST, cs[st], st < 2 ? 2.0 : 1.0);
+      }
+      return;
+    }
+    if (c->p.scheme == MHD_PC) {
+      phase_a(state());
+      phase_b(state(), trhs(), true);
+      combine(CB_PC_PRED, dt, 0.0, first ? 1.0 : 1.5, first ? 0.0 : -0.5);
+      phase_a(tstate());
+      phase_b(tstate(), trhs(), false);
+      combine(CB_PC_CORR, 0.5 * dt, 0.0);
+      return;
+    }
+    ms.a_cur[0] = first ? 1.0 : 1.5;
+    ms.a_prev[0] = first ? 0.0 : -0.5;
+    phase_a(state());
+    phase_b(state(), nullptr);
   }
 
   void reset_status() {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(kStatusWords), 0, c->stream, status(), kStatusWords, 0u);
+    const int words = kStatusSlots * 2 * 2;  // doubles as u32 words; +0.0 is all-zero bits
+    hipLaunchKernelGGL(k_fill_u32, dim3((words + kThreads - 1) / kThreads), dim3(kThreads), 0, c->stream,
+                       reinterpret_cast<unsigned*>(status()), words, 0u);
   }
 
   // Diagnostics pass over the state: real-space partials and spectral sums.
@@ -675,6 +927,9 @@ struct Engine {
     const unsigned maxmask = (1u << DQ_DIVB_MAX) | (1u << DQ_CFL_MAX);
     hipLaunchKernelGGL(k_reduce, dim3(kDiagQ + kSpecQ), dim3(kThreads), 0, c->stream, part(), (int64_t)grid.x,
                        kDiagQ, maxmask, spart(), (int64_t)sblocks, kSpecQ, res(), res() + 16);
+    // the steps' status slots: FP64 max of the signal speeds, sum of the non-finite counts
+    hipLaunchKernelGGL(k_reduce, dim3(2), dim3(kThreads), 0, c->stream, status(), (int64_t)kStatusSlots, 2, 1u,
+                       status(), (int64_t)0, 0, res() + kResStatus, res() + kResStatus);
   }
 };
 
@@ -703,7 +958,8 @@ int with_engine(mhd_ctx* c, F&& fn) {
 int validate(const mhd_params* p) {
   if (!p) return MHD_E_ARG;
   if (p->precision != MHD_FP32 && p->precision != MHD_FP64 && p->precision != MHD_MIXED) return MHD_E_ARG;
-  if (p->reserved != 0) return MHD_E_ARG;
+  if (p->scheme != MHD_AB2 && p->scheme != MHD_RK4 && p->scheme != MHD_PC) return MHD_E_ARG;
+  if (!std::isfinite(p->force)) return MHD_E_ARG;
   if (!(p->gamma > 1.0) || !(p->nu >= 0.0) || !(p->eta >= 0.0) || !(p->dt > 0.0) || !(p->cfl > 0.0)) return MHD_E_ARG;
   if (!std::isfinite(p->gamma) || !std::isfinite(p->nu) || !std::isfinite(p->eta) || !std::isfinite(p->dt) ||
       !std::isfinite(p->cfl))
@@ -713,6 +969,16 @@ int validate(const mhd_params* p) {
 }
 
 bool dtype_ok(int32_t d) { return d == MHD_FP32 || d == MHD_FP64; }
+
+// Ensemble members: AB2 without the Section V variants (their batched
+// launches carry per-member AB2 coefficients only).
+int validate_member(const mhd_params* p) {
+  const int v = validate(p);
+  if (v != MHD_OK) return v;
+  if (p->scheme != MHD_AB2 || p->force != 0.0 || (p->flags & (MHD_FLAG_VISC_LAPLACIAN | MHD_FLAG_KINEMATIC)))
+    return MHD_E_ARG;
+  return MHD_OK;
+}
 
 }  // namespace
 
@@ -804,10 +1070,7 @@ static int ctx_diag(mhd_ctx* c, mhd_diag* h) {
   });
   if (rc != MHD_OK) return rc;
   double res[kResWords];
-  unsigned st[kStatusWords];
   hipError_t err = hipMemcpyAsync(res, c->ws + c->L.res, sizeof(res), hipMemcpyDeviceToHost, c->stream);
-  if (err == hipSuccess)
-    err = hipMemcpyAsync(st, c->ws + c->L.status, sizeof(st), hipMemcpyDeviceToHost, c->stream);
   if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
   if (err != hipSuccess) return hip_fail(c, err, "mhd_diagnostics copy");
   const Geo& g = c->g;
@@ -842,14 +1105,80 @@ static int ctx_diag(mhd_ctx* c, mhd_diag* h) {
   h->mach_s = umean / h->c_s;
   h->mach_a = h->v_a > 0 ? umean / h->v_a : INFINITY;
   h->nonfinite = (int64_t)res[DQ_NONFINITE];
-  float cmax_seen;
-  std::memcpy(&cmax_seen, &st[0], sizeof(float));
-  if (h->nonfinite > 0 || st[1] > 0 || !(cmax_seen == cmax_seen)) return MHD_E_NONFINITE;
+  const double cmax_seen = res[kResStatus], bad_seen = res[kResStatus + 1];
+  if (h->nonfinite > 0 || bad_seen > 0 || !(cmax_seen == cmax_seen)) return MHD_E_NONFINITE;
   if ((c->p.flags & MHD_FLAG_CHECK_CFL) && cmax_seen > 0) {
-    const double dt_lim = c->p.cfl * (two_pi / g.n) / (double)cmax_seen;
+    const double dt_lim = c->p.cfl * (two_pi / g.n) / cmax_seen;
     if (c->p.dt > dt_lim) return MHD_E_CFL;
   }
   return MHD_OK;
+}
+
+// The steady AB2 step (coefficients 3/2, -1/2) captured once as a graph on a
+// private stream (the caller's stream may be the legacy default stream, which
+// cannot be captured) and replayed by mhd_step.  The step's launches never
+// change: the workspace, the parameters and the launch geometry are fixed for
+// the context's lifetime.
+static int ctx_capture(mhd_ctx* c) {
+  hipError_t e = hipSuccess;
+  if (!c->cap) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(c, e, "graph stream");
+  e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamBeginCapture");
+  hipStream_t saved = c->stream;
+  c->stream = c->cap;
+  (void)with_engine(c, [&](auto& eng) {
+    eng.step_once(false);
+    return MHD_OK;
+  });
+  c->stream = saved;
+  hipGraph_t g = nullptr;
+  const hipError_t le = hipGetLastError();
+  e = hipStreamEndCapture(c->cap, &g);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_fail(c, le != hipSuccess ? le : e, "step capture");
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(c, e, "hipGraphInstantiate");
+  }
+  c->graph = g;
+  c->exec = x;
+  return MHD_OK;
+}
+
+// Checkpoint blob: header, then the compact state U^n, the AB2 history
+// R^{n-1} and the status slots, each at a 256-byte boundary.
+struct CkptLayout {
+  size_t state, rprev, status, total, spec_bytes, status_bytes;
+};
+static CkptLayout ckpt_layout(const mhd_ctx* c) {
+  CkptLayout B;
+  const size_t ts = is_fp32(c->p.precision) ? sizeof(float) : sizeof(double);
+  B.spec_bytes = 8 * (size_t)c->g.sc * 2 * ts;
+  B.status_bytes = (size_t)kStatusSlots * 2 * sizeof(double);
+  size_t off = sizeof(CkptHeader);
+  B.state = off;
+  off += align256(B.spec_bytes);
+  B.rprev = off;
+  off += align256(B.spec_bytes);
+  B.status = off;
+  off += align256(B.status_bytes);
+  B.total = off;
+  return B;
+}
+
+// *out += hash of the blob's 64-bit words (the checksum word read as zero);
+// the caller zeroes *out first where it starts a new hash.
+static void blob_hash(mhd_ctx* c, const char* blob, size_t bytes, unsigned long long* out) {
+  const int64_t words = (int64_t)(bytes / sizeof(uint64_t));
+  int64_t blocks = (words + kThreads * 8 - 1) / (kThreads * 8);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_blob_hash, dim3((unsigned)blocks), dim3(kThreads), 0, c->stream,
+                     reinterpret_cast<const uint64_t*>(blob), words, (int64_t)kCkptSumWord, out);
 }
 
 // ------------------------------------------------------------------ ensembles
@@ -1151,22 +1480,98 @@ int mhd_rhs(mhd_ctx* c, const void* d_in, void* d_out, int32_t dtype) {
 int mhd_step(mhd_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return MHD_E_ARG;
   if (!c->has_state) return MHD_E_STATE;
+  // Eager launches for the Euler start, while profiling (events bracket single
+  // launches) or with graphs turned off; every other step replays the graph.
+  int done = 0;
   int rc = with_engine(c, [&](auto& e) {
-    for (int s = 0; s < nsteps; ++s) {
-      const bool first = c->first_step && s == 0;
-      e.ms.a_cur[0] = first ? 1.0 : 1.5;
-      e.ms.a_prev[0] = first ? 0.0 : -0.5;
-      e.phase_a(e.state());
-      e.phase_b(e.state(), nullptr);
+    for (; done < nsteps; ++done) {
+      const bool first = c->first_step && done == 0;
+      if (!first && !c->prof_on && !(c->p.flags & MHD_FLAG_NO_GRAPH)) break;
+      e.step_once(first);
     }
     return check_launch(c, "mhd_step");
   });
+  if (rc == MHD_OK && done < nsteps) {
+    if (!c->exec) rc = ctx_capture(c);
+    for (int s = done; rc == MHD_OK && s < nsteps; ++s) {
+      const hipError_t e = hipGraphLaunch(c->exec, c->stream);
+      if (e != hipSuccess) rc = hip_fail(c, e, "hipGraphLaunch");
+    }
+  }
   if (rc == MHD_OK && nsteps > 0) {
     c->first_step = false;
     c->step += nsteps;
     c->t += nsteps * c->p.dt;
   }
   return rc;
+}
+
+size_t mhd_checkpoint_bytes(const mhd_ctx* c) {
+  if (!c) return 0;
+  return ckpt_layout(c).total;
+}
+
+int mhd_save(mhd_ctx* c, void* d_blob) {
+  if (!c || !d_blob || (reinterpret_cast<uintptr_t>(d_blob) & 255u) != 0) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  const CkptLayout B = ckpt_layout(c);
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, "MHDCKPT", 8);
+  h.version = kCkptVersion;
+  h.n = c->p.n;
+  h.precision = c->p.precision;
+  h.first_step = c->first_step ? 1 : 0;
+  h.step = c->step;
+  h.t = c->t;
+  h.dt = c->p.dt;
+  h.payload_bytes = B.total - sizeof(CkptHeader);
+  h.sc = (uint64_t)c->g.sc;
+  char* blob = static_cast<char*>(d_blob);
+  hipLaunchKernelGGL(k_write_header, dim3(1), dim3(64), 0, c->stream, h, reinterpret_cast<CkptHeader*>(blob));
+  hipError_t e = hipMemcpyAsync(blob + B.state, c->ws + c->L.state, B.spec_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(blob + B.rprev, c->ws + c->L.rprev, B.spec_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(blob + B.status, c->ws + c->L.status, B.status_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mhd_save copy");
+  blob_hash(c, blob, B.total, reinterpret_cast<unsigned long long*>(blob) + kCkptSumWord);
+  return check_launch(c, "mhd_save");
+}
+
+int mhd_load(mhd_ctx* c, const void* d_blob) {
+  if (!c || !d_blob || (reinterpret_cast<uintptr_t>(d_blob) & 255u) != 0) return MHD_E_ARG;
+  const CkptLayout B = ckpt_layout(c);
+  const char* blob = static_cast<const char*>(d_blob);
+  CkptHeader h;
+  unsigned long long* hash = reinterpret_cast<unsigned long long*>(c->ws + c->L.hash);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(2), 0, c->stream, reinterpret_cast<unsigned*>(hash), 2, 0u);
+  hipError_t e = hipMemcpyAsync(&h, blob, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mhd_load header");
+  if (std::memcmp(h.magic, "MHDCKPT", 8) != 0 || h.version != kCkptVersion ||
+      h.payload_bytes != B.total - sizeof(CkptHeader) || h.sc != (uint64_t)c->g.sc)
+    return MHD_E_STATE;
+  blob_hash(c, blob, B.total, hash);
+  unsigned long long sum = 0;
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(&sum, hash, sizeof(sum), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mhd_load checksum");
+  if (sum != h.checksum) return MHD_E_STATE;
+  // a valid blob of another configuration
+  if (h.n != c->p.n || h.precision != c->p.precision || h.dt != c->p.dt) return MHD_E_ARG;
+  e = hipMemcpyAsync(c->ws + c->L.state, blob + B.state, B.spec_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + c->L.rprev, blob + B.rprev, B.spec_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + c->L.status, blob + B.status, B.status_bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mhd_load copy");
+  c->has_state = true;
+  c->first_step = h.first_step != 0;
+  c->step = h.step;
+  c->t = h.t;
+  return MHD_OK;
 }
 
 int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) { return ctx_diag(c, h); }
@@ -1241,6 +1646,9 @@ double mhd_step_bytes(const mhd_ctx* cc) {
 int mhd_destroy(mhd_ctx* c) {
   if (!c) return MHD_OK;
   for (auto& e : c->ev) (void)hipEventDestroy(e);
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
   return MHD_OK;
 }
@@ -1261,10 +1669,27 @@ const char* mhd_status_string(int s) {
 
 const char* mhd_last_error(const mhd_ctx* c) { return c ? c->last_err.c_str() : ""; }
 
+int mhd_bench_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_stream) {
+  if (!d_src || !d_dst || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(d_src) & 15u) ||
+      (reinterpret_cast<uintptr_t>(d_dst) & 15u))
+    return MHD_E_ARG;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return MHD_E_HIP;
+  const int64_t words = (int64_t)(bytes / 16);
+  int64_t blocks = (int64_t)cus * 8;  // eight resident 256-thread workgroups per CU
+  const int64_t need = (words + kThreads - 1) / kThreads;
+  if (blocks > need) blocks = need < 1 ? 1 : need;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(kThreads), 0, static_cast<hipStream_t>(hip_stream),
+                     static_cast<const uint4*>(d_src), static_cast<uint4*>(d_dst), words);
+  return hipGetLastError() == hipSuccess ? MHD_OK : MHD_E_HIP;
+}
+
 size_t mhd_ens_workspace_bytes(const mhd_params* p, int32_t count) {
   if (!p || count < 1) return 0;
   for (int i = 0; i < count; ++i)
-    if (validate(&p[i]) != MHD_OK) return 0;
+    if (validate_member(&p[i]) != MHD_OK) return 0;
   std::vector<EnsGroup> groups;
   std::vector<int> grp_of;
   return ens_plan(p, count, groups, grp_of);
@@ -1276,7 +1701,7 @@ int mhd_ens_init(const mhd_params* p, int32_t count, void* d_workspace, size_t w
   *out = nullptr;
   if (!p || count < 1) return MHD_E_ARG;
   for (int i = 0; i < count; ++i) {
-    const int v = validate(&p[i]);
+    const int v = validate_member(&p[i]);
     if (v != MHD_OK) return v;
   }
   mhd_ens* E = new (std::nothrow) mhd_ens();
@@ -1317,6 +1742,10 @@ int mhd_ens_init(const mhd_params* p, int32_t count, void* d_workspace, size_t w
       break;
     }
     G.lead->stream = G.stream;
+    G.lead->ev.clear();  // the lead shares no events, graph or stream with member 0
+    G.lead->cap = nullptr;
+    G.lead->graph = nullptr;
+    G.lead->exec = nullptr;
   }
   if (rc == MHD_OK) {
     hipError_t e = hipStreamCreateWithFlags(&E->cap, hipStreamNonBlocking);

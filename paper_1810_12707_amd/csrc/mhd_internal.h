@@ -26,6 +26,7 @@ constexpr int kRowFields = 16; // fields held by one row (x) pass
 constexpr int kDiagQ = 14;     // diagnostic partial sums per block
 constexpr int kDiagFields = 9;  // real-space inputs of the diagnostics pass: the state and div B
 constexpr int kSpecQ = 3;      // spectral diagnostic partial sums per block
+constexpr int kStatusSlots = 2048;  // per-workgroup status slots of the flux pass (grid is capped to this)
 
 // Index of each real-space diagnostic partial.
 enum DiagQ {
@@ -103,6 +104,15 @@ struct RhsArgs {
   T* rprev;               // compact [8][sc] (R^{n-1}, overwritten with R^n)
   T* rout;                // if non-null: store R here, leave state/rprev untouched
   const T* tw;
+  // Section V variants (single runs only, so scalars): mu != 0 adds the
+  // viscous force -mu |k|^2 u^ to R_m and -mu |k|^2 q^ to R_E, q = |u|^2/2,
+  // from uhat [4][sc] (u^x, u^y, u^z, q^); force: [4][sc] body-force spectra
+  // added to R_m and R_E, or null; kinematic: R_rho, R_m, R_E are zero
+  const T* uhat;
+  const T* force;
+  double mu;
+  int32_t kinematic;
+  int32_t pad2;
   Geo g;
   Batch bt;
   // per member: time step, AB2 coefficients of R^n and R^{n-1}, diffusivity
@@ -122,7 +132,8 @@ struct RowArgs {
   int32_t real_dtype;       // 0 = double, 1 = float
   int32_t nf;               // fields of an I/O pass
   double* partials;         // per-block records (RM_XDIAG, single member)
-  unsigned* status;         // [0] max CFL speed (float bits), [1] non-finite count (RM_XB)
+  double* status;           // RM_XB: status slots [kStatusSlots][2] (max signal speed, non-finite
+                            // count), slot = workgroup id; null: no status (pure RHS evaluations)
   const T* tw;
   Geo g;
   Batch bt;

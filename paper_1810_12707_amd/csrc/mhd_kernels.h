@@ -420,8 +420,11 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
     };
     fft_reg<T, PL, C, NT, C, 1, -1, 0, 0, true>(tile, stw, tid, C, load, store);
   }
-  // epilogue over this thread's last-pass positions: resistive term, update
+  // epilogue over this thread's last-pass positions: resistive term, the
+  // Section V variants (block-uniform branches), update
   const T eta = T(a.eta[mem]);
+  const bool induction = f >= 4 && f <= 6;
+  const int vslot = f <= 3 ? f - 1 : 3;  // u^_{f-1} for the momentum, q^ for the energy
 #pragma unroll
   for (int i = 0; i < LP::CNT; ++i) {
 #pragma unroll
@@ -431,12 +434,22 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
       if (idx < 0) continue;
       if constexpr (!PRE) load_old(i, r);
       cx<T> R = acc[i][r];
-      if (f >= 4 && f <= 6) {
+      const T k2 = T(kx * kx + ky * ky + kz * kz);
+      if (induction) {
         // MHD4 resistive term: - eta |k|^2 B^
-        const T k2 = T(kx * kx + ky * ky + kz * kz);
         const cx<T> b = u_pre[i][r];
         R.x -= eta * k2 * b.x;
         R.y -= eta * k2 * b.y;
+      } else {
+        const int64_t off = idx - f * sc;  // position inside one compact field
+        if (a.mu != 0.0) {
+          // viscous force mu lap u, and mu lap(|u|^2/2) in the energy
+          const cx<T> v = ld(member_ptr(a.uhat, mem, ms), vslot * sc + off);
+          R.x -= T(a.mu) * k2 * v.x;
+          R.y -= T(a.mu) * k2 * v.y;
+        }
+        if (a.force) R = cadd(R, ld(member_ptr(a.force, mem, ms), vslot * sc + off));
+        if (a.kinematic) R = mk<T>(0, 0);  // frozen rho u and E
       }
       finish(idx, R, u_pre[i][r], r_pre[i][r]);
     }
@@ -485,28 +498,62 @@ __device__ __forceinline__ double block_reduce(double v, bool is_max, double* s,
   return s[0];
 }
 
+// Error-free sum of s and x (Neumaier's two-sum): s <- fl(s + x), the
+// rounding error of that addition added to the compensation c.
+__device__ __forceinline__ void neumaier_add(double& s, double& c, double x) {
+  const double t = s + x;
+  if (fabs(s) >= fabs(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+// Compensated fixed-order tree sum over the block of per-thread (sum,
+// compensation) pairs; every level adds with neumaier_add, so the block
+// result carries the same compensation as a serial Neumaier sum.  s: 2 NT
+// doubles of LDS scratch.  The result (s + c) is valid in thread 0.
+template <int NT = kThreads>
+__device__ __forceinline__ double block_sum_comp(double v, double cv, double* s, int tid) {
+  __syncthreads();
+  s[tid] = v;
+  s[NT + tid] = cv;
+  __syncthreads();
+  for (int w = NT / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      double a = s[tid], ca = s[NT + tid] + s[NT + tid + w];
+      neumaier_add(a, ca, s[tid + w]);
+      s[tid] = a;
+      s[NT + tid] = ca;
+    }
+    __syncthreads();
+  }
+  return s[0] + s[NT];
+}
+
 // Persistent: workgroup w handles row pairs w, w + G, w + 2G, ... (G = grid
 // size, sized by the host to the number of resident workgroups).  For the
 // spectral-input modes the global loads of the next row pair's first FFT pass
 // are issued right after the current pair's first pass, so they are in flight
 // during the current pair's LDS passes, pointwise work and stores.
-// Fold a workgroup's CFL speed and non-finite count into a member's status
-// words: an unsigned max over the bit patterns of non-negative floats orders
-// them like the floats (NaN sorts above every finite value), and integer adds
-// commute, so the result does not depend on block order.  Block-uniform call.
-// s_red: NT doubles of LDS scratch, which may alias the caller's row buffer
-// (the reductions begin and end with a barrier).
-template <int NT, typename T>
-__device__ __forceinline__ void flush_status(T cfl, int bad, unsigned* status, double* s_red) {
+// Fold a workgroup's CFL speed and non-finite count into its own status slot
+// of a member (slot = workgroup id; kStatusSlots slots of two doubles: the
+// largest signal speed seen by any step since the state was set, and the
+// count of non-finite points).  The speed is reduced in FP64 (a max, exact in
+// any precision, NaN propagating) and kept as a running max over steps; each
+// slot has a single writer, so no atomics are needed and the result does not
+// depend on workgroup order.  Block-uniform call.  s_red: NT doubles of LDS
+// scratch, which may alias the caller's row buffer (the reductions begin and
+// end with a barrier).
+template <int NT>
+__device__ __forceinline__ void flush_status(double cfl, int bad, double* slots, double* s_red) {
   const int tid = threadIdx.x;
-  const double cfl_b = block_reduce<NT>(double(cfl), true, s_red, tid);
+  const double cfl_b = block_reduce<NT>(cfl, true, s_red, tid);
   const double bad_b = block_reduce<NT>(double(bad), false, s_red, tid);
   __syncthreads();  // every thread has read the results before the scratch is reused
   if (tid == 0) {
-    const float cf = float(cfl_b);
-    const unsigned bits = (cf != cf) ? 0x7fc00000u : (cf > 0.f ? __float_as_uint(cf) : 0u);
-    atomicMax(&status[0], bits);
-    if (bad_b > 0) atomicAdd(&status[1], (unsigned)bad_b);
+    double* const slot = slots + 2 * (int64_t)blockIdx.x;
+    const double old = slot[0];
+    slot[0] = !(cfl_b <= old) ? cfl_b : old;
+    slot[1] = slot[1] + bad_b;
   }
 }
 
@@ -581,14 +628,16 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   // block reductions (status words, diagnostics) use the row buffer as scratch
   // when it is large enough (each begins with a barrier, after which no row
   // work touches the buffer); small sizes get their own array
-  constexpr bool RED_IN_BUF = sizeof(cx<T>) * NB * BS >= NT * sizeof(double);
-  __shared__ double red_own[RED_IN_BUF ? 1 : NT];
+  constexpr bool RED_IN_BUF = sizeof(cx<T>) * NB * BS >= 2 * NT * sizeof(double);
+  __shared__ double red_own[RED_IN_BUF ? 1 : 2 * NT];
   double* const red = RED_IN_BUF ? reinterpret_cast<double*>(buf) : red_own;
   const int tid = threadIdx.x;
   const int64_t rows_per_mem = (int64_t)N * N / 2;
   const int64_t nitems = rows_per_mem * a.bt.nmem;
   const int nin = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NIN;
-  const int nout = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL) ? a.nf : RowShape<MODE>::NOUT;
+  const int nout = (MODE == RM_XFWD_REAL || MODE == RM_XINV_REAL)
+                       ? a.nf
+                       : ((MODE == RM_XA && a.nf == 4) ? 4 : RowShape<MODE>::NOUT);
   load_twiddles<T, N, NT>(stw, a.tw, tid);
   auto lds_store = [&](int, int, int fld, int q, cx<T> v) { buf[at(fld, q)] = v; };
 
@@ -632,12 +681,18 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
       }
     }
   };
-  // per-workgroup accumulators of the diagnostic / status modes
-  T cfl = T(0);
+  // per-workgroup accumulators of the diagnostic / status modes: the largest
+  // signal speed (each point's speed is formed in T; the max is held in FP64)
+  // and the non-finite count of the flux pass; Neumaier (sum, compensation)
+  // pairs of the diagnostics pass
+  double cfl = 0.0;
   int bad = 0;
-  double q[kDiagQ];
+  double q[kDiagQ], qc[kDiagQ];
 #pragma unroll
-  for (int i = 0; i < kDiagQ; ++i) q[i] = 0.0;
+  for (int i = 0; i < kDiagQ; ++i) {
+    q[i] = 0.0;
+    qc[i] = 0.0;
+  }
 
   int64_t item = blockIdx.x;
   if constexpr (SPEC_IN) {
@@ -649,9 +704,9 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     const int64_t row0 = 2 * (item - mem * rows_per_mem);  // flattened row z*N + y of the first row
     if constexpr (MODE == RM_XB) {
       if (mem != cur_m) {  // uniform across the workgroup
-        if (cur_m >= 0) {
+        if (cur_m >= 0 && a.status) {
           flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
-          cfl = T(0);
+          cfl = 0.0;
           bad = 0;
         }
         cur_m = mem;
@@ -766,15 +821,21 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     }
 
     if constexpr (MODE == RM_XA) {
-      // u = m / rho, both rows at once
+      // u = m / rho, both rows at once; with four outputs also q = |u|^2/2
+      // (the viscous-force variant's energy term) into the slot m_z vacated
       for (int x = tid; x < N; x += NT) {
         const cx<T> rho = buf[at(0, x)];
         const T i0 = recip_(rho.x), i1 = recip_(rho.y);
+        cx<T> u[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           const cx<T> m = buf[at(1 + i, x)];
-          buf[at(i, x)] = mk<T>(m.x * i0, m.y * i1);
+          u[i] = mk<T>(m.x * i0, m.y * i1);
+          buf[at(i, x)] = u[i];
         }
+        if (nout == 4)
+          buf[at(3, x)] = mk<T>(T(0.5) * (u[0].x * u[0].x + u[1].x * u[1].x + u[2].x * u[2].x),
+                                T(0.5) * (u[0].y * u[0].y + u[1].y * u[1].y + u[2].y * u[2].y));
       }
     }
 
@@ -830,7 +891,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           // fastest signal speed for the CFL limit, and a non-finite check
           const T umax = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
           const T c = umax + sqrt_((gam * P + B2) * ir);
-          if (!(c <= cfl)) cfl = c;  // NaN propagates
+          if (!(double(c) <= cfl)) cfl = double(c);  // NaN propagates
           const bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) &&
                            finite_(By) && finite_(Bz) && finite_(E);
           bad += fin ? 0 : 1;
@@ -854,17 +915,18 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           const double B2 = Bx * Bx + By * By + Bz * Bz;
           const double mu = mx * ux + my * uy + mz * uz;
           const double P = gm1 * (E - 0.5 * mu - 0.5 * B2);
-          q[DQ_RHO] += rho;
-          q[DQ_MX] += mx;
-          q[DQ_MY] += my;
-          q[DQ_MZ] += mz;
-          q[DQ_EKIN] += 0.5 * mu;
-          q[DQ_EMAG] += 0.5 * B2;
-          q[DQ_P] += P;
-          q[DQ_E] += E;
-          q[DQ_HC] += ux * Bx + uy * By + uz * Bz;
-          q[DQ_UABS] += sqrt(ux * ux + uy * uy + uz * uz);
-          q[DQ_BABS] += sqrt(B2);
+          auto acc = [&](int i, double x) { neumaier_add(q[i], qc[i], x); };
+          acc(DQ_RHO, rho);
+          acc(DQ_MX, mx);
+          acc(DQ_MY, my);
+          acc(DQ_MZ, mz);
+          acc(DQ_EKIN, 0.5 * mu);
+          acc(DQ_EMAG, 0.5 * B2);
+          acc(DQ_P, P);
+          acc(DQ_E, E);
+          acc(DQ_HC, ux * Bx + uy * By + uz * Bz);
+          acc(DQ_UABS, sqrt(ux * ux + uy * uy + uz * uz));
+          acc(DQ_BABS, sqrt(B2));
           const double adb = fabs(dB);
           if (!(adb <= q[DQ_DIVB_MAX])) q[DQ_DIVB_MAX] = adb;
           const double c = fmax(fabs(ux), fmax(fabs(uy), fabs(uz))) + sqrt((gam * P + B2) / rho);
@@ -911,11 +973,12 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   }
 
   if constexpr (MODE == RM_XB) {
-    if (cur_m >= 0) flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
+    if (cur_m >= 0 && a.status) flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
   }
   if constexpr (MODE == RM_XDIAG) {
     for (int i = 0; i < kDiagQ; ++i) {
-      const double r = block_reduce<NT>(q[i], i == DQ_DIVB_MAX || i == DQ_CFL_MAX, red, tid);
+      const bool is_max = i == DQ_DIVB_MAX || i == DQ_CFL_MAX;
+      const double r = is_max ? block_reduce<NT>(q[i], true, red, tid) : block_sum_comp<NT>(q[i], qc[i], red, tid);
       if (tid == 0) a.partials[(int64_t)blockIdx.x * kDiagQ + i] = r;
     }
   }

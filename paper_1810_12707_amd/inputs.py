@@ -224,6 +224,72 @@ def orszag_tang(n: int = 1024, nu: float = 5e-4, eta: float = 5e-4, steps: int =
     return Case(name, U, gamma, nu, eta, cfl_dt(U, gamma), steps, {})
 
 
+def compressive_state(n: int, seed: int, gamma: float = 5.0 / 3.0) -> np.ndarray:
+    """A test start whose right-hand side is well conditioned in FP32: a
+    general (half compressive) velocity of rms 0.5 in shells 1-4, solenoidal
+    B of rms 0.3, rho = 1 + 20% and P = 0.6 + 0.1 rms noise in shells 1-4 (a
+    modest background pressure, so -div F^E is not a small difference of
+    large terms, and div m is not that of a nearly solenoidal flow)."""
+    u = random_field(n, seed, 3, 1, 4, 0.5, solenoidal=False)
+    B = random_field(n, seed + 1, 3, 1, 4, 0.3)
+    d = random_field(n, seed + 2, 1, 1, 4, 1.0, solenoidal=False)[0]
+    rho = 1.0 + 0.2 * d / float(np.max(np.abs(d)))
+    P = 0.6 + random_field(n, seed + 3, 1, 1, 4, 0.1, solenoidal=False)[0]
+    return conserved(rho, u, B, P, gamma)
+
+
+@dataclass
+class TrigState:
+    """Primitive fields that are trigonometric polynomials with wavevectors in
+    {-1, 0, 1}^3 (degree <= 1 per axis): each field is a constant plus a few
+    terms amp * cos(k.x + phase).  B_i depends only on the two coordinates
+    other than x_i, so div B = 0 exactly."""
+    terms: dict  # name -> (constant, [(amp, (kx, ky, kz), phase), ...])
+
+    def evaluate(self, name: str, z, y, x, xp=np):
+        c0, ts = self.terms[name]
+        out = c0 + 0.0 * (x + y + z)
+        for amp, (kx, ky, kz), ph in ts:
+            out = out + amp * xp.cos(kx * x + ky * y + kz * z + ph)
+        return out
+
+    def conserved(self, z, y, x, gamma: float, xp=np):
+        """rho, m = rho u, B, E = P/(gamma-1) + rho|u|^2/2 + |B|^2/2 at the
+        given coordinates (numpy or torch arrays), stacked (8, ...)."""
+        rho = self.evaluate("rho", z, y, x, xp)
+        u = [self.evaluate(f"u{i}", z, y, x, xp) for i in range(3)]
+        B = [self.evaluate(f"B{i}", z, y, x, xp) for i in range(3)]
+        P = self.evaluate("P", z, y, x, xp)
+        E = P / (gamma - 1.0) + 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + \
+            0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2])
+        return xp.stack([rho, rho * u[0], rho * u[1], rho * u[2], B[0], B[1], B[2], E])
+
+
+def trig_state(seed: int, rho_amp: float = 0.15, u_amp: float = 0.4, b_amp: float = 0.4,
+               p_amp: float = 0.1, p0: float = 1.0) -> TrigState:
+    """Random TrigState (numpy's seeded generator): three terms per field.
+    With m = rho u and E as in TrigState.conserved every flux of Eqs.
+    MHD1-MHD4 is a trigonometric polynomial of degree <= 4 per axis, so the
+    right-hand side is the same polynomial on every grid with n >= 13."""
+    rng = np.random.default_rng(seed)
+
+    def terms(scale, kset=None):
+        out = []
+        for _ in range(3):
+            k = [int(v) for v in rng.integers(-1, 2, size=3)]
+            if kset is not None:
+                k = [k[j] if kset[j] else 0 for j in range(3)]
+            out.append((float(rng.uniform(-1, 1) * scale), tuple(k), float(rng.uniform(0, 2 * np.pi))))
+        return out
+
+    t = {"rho": (1.0, terms(rho_amp / 3)), "P": (p0, terms(p_amp / 3))}
+    for i in range(3):
+        t[f"u{i}"] = (float(rng.uniform(-0.2, 0.2)), terms(u_amp / 3))
+        mask = [j != i for j in range(3)]  # (x, y, z): B_i independent of x_i
+        t[f"B{i}"] = (float(rng.uniform(-0.3, 0.3)), terms(b_amp / 3, mask))
+    return TrigState(t)
+
+
 # The workloads of the paper's 3D MHD runs as concrete synthetic inputs.
 def config_small(n: int = 32) -> Case:
     """32^3 ABC-flow start, B rms 1e-3 in shells 1-4 (seed 0), Mach 0.1,

@@ -21,11 +21,17 @@ MHD_OK, MHD_E_ARG, MHD_E_SIZE, MHD_E_WORKSPACE, MHD_E_HIP, MHD_E_NONFINITE, MHD_
     0, -1, -2, -3, -4, -5, -6, -7)
 MHD_FP64, MHD_FP32, MHD_MIXED = 0, 1, 2
 MHD_FLAG_CHECK_CFL = 1
+MHD_FLAG_NO_GRAPH = 2
+MHD_FLAG_VISC_LAPLACIAN = 4
+MHD_FLAG_KINEMATIC = 8
+MHD_AB2, MHD_RK4, MHD_PC = 0, 1, 2
+SCHEMES = {"ab2": MHD_AB2, "rk4": MHD_RK4, "pc": MHD_PC}
 
 EXPORTED = (
     "mhd_supported_size", "mhd_workspace_bytes", "mhd_init", "mhd_set_state", "mhd_get_state",
     "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_spectrum_pitch", "mhd_destroy",
     "mhd_status_string", "mhd_last_error", "mhd_profile", "mhd_profile_read", "mhd_step_bytes",
+    "mhd_checkpoint_bytes", "mhd_save", "mhd_load", "mhd_bench_copy",
     "mhd_ens_workspace_bytes", "mhd_ens_init", "mhd_ens_set_state", "mhd_ens_get_state", "mhd_ens_step",
     "mhd_ens_diagnostics", "mhd_ens_num_groups", "mhd_ens_group_info", "mhd_ens_step_bytes", "mhd_ens_destroy",
     "mhd_ens_last_error",
@@ -38,8 +44,9 @@ PASS_NAMES = ("zinv_a", "yinv_a", "xa", "yfwd_a", "zfwd_a", "zinv_b", "yinv_b", 
 class mhd_params(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
+        ("scheme", ctypes.c_int32), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
         ("eta", ctypes.c_double), ("dt", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("force", ctypes.c_double),
     ]
 
 
@@ -106,6 +113,12 @@ def lib() -> ctypes.CDLL:
         L.mhd_profile_read.restype = ctypes.c_int
         L.mhd_step_bytes.argtypes = [vp]
         L.mhd_step_bytes.restype = ctypes.c_double
+        L.mhd_checkpoint_bytes.argtypes = [vp]
+        L.mhd_checkpoint_bytes.restype = ctypes.c_size_t
+        L.mhd_save.argtypes = [vp, vp]
+        L.mhd_bench_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.mhd_bench_copy.restype = ctypes.c_int
+        L.mhd_load.argtypes = [vp, vp]
         i32 = ctypes.c_int32
         L.mhd_ens_workspace_bytes.argtypes = [P, i32]
         L.mhd_ens_workspace_bytes.restype = ctypes.c_size_t
@@ -124,7 +137,8 @@ def lib() -> ctypes.CDLL:
         L.mhd_ens_last_error.argtypes = [vp]
         L.mhd_ens_last_error.restype = ctypes.c_char_p
         for name in ("mhd_supported_size", "mhd_init", "mhd_set_state", "mhd_get_state", "mhd_rhs",
-                     "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_destroy", "mhd_ens_init",
+                     "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_destroy", "mhd_save", "mhd_load",
+                     "mhd_ens_init",
                      "mhd_ens_set_state", "mhd_ens_get_state", "mhd_ens_step", "mhd_ens_diagnostics",
                      "mhd_ens_group_info", "mhd_ens_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -136,9 +150,12 @@ def status_string(status: int) -> str:
     return lib().mhd_status_string(int(status)).decode()
 
 
-def make_params(n, precision=MHD_FP32, gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=1e-3, cfl=0.1, flags=0) -> mhd_params:
-    return mhd_params(int(n), int(precision), int(flags), 0, float(gamma), float(nu), float(eta), float(dt),
-                      float(cfl))
+def make_params(n, precision=MHD_FP32, gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=1e-3, cfl=0.1, flags=0,
+                scheme=MHD_AB2, force=0.0) -> mhd_params:
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    return mhd_params(int(n), int(precision), int(flags), int(scheme), float(gamma), float(nu), float(eta),
+                      float(dt), float(cfl), float(force))
 
 
 # ---------------------------------------------------------------- same-name wrappers
@@ -248,6 +265,32 @@ def mhd_step_bytes(ctx) -> float:
     return float(lib().mhd_step_bytes(ctx))
 
 
+def mhd_bench_copy(src, dst, stream_handle: int):
+    """One streaming copy of src into dst (CUDA tensors of equal byte size)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _rc(lib().mhd_bench_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                             ctypes.c_void_p(stream_handle)), "mhd_bench_copy")
+
+
+def mhd_checkpoint_bytes(ctx) -> int:
+    return int(lib().mhd_checkpoint_bytes(ctx))
+
+
+def mhd_save(ctx, blob):
+    """blob: uint8 CUDA tensor of >= mhd_checkpoint_bytes(ctx) bytes, 256-byte aligned."""
+    _rc(lib().mhd_save(ctx, ctypes.c_void_p(blob.data_ptr())), "mhd_save", ctx)
+
+
+def mhd_load(ctx, blob) -> int:
+    """Returns the status (MHD_OK, or MHD_E_STATE / MHD_E_ARG for a blob that
+    is not a valid checkpoint of this configuration); raises on other errors."""
+    rc = lib().mhd_load(ctx, ctypes.c_void_p(blob.data_ptr()))
+    if rc not in (MHD_OK, MHD_E_STATE, MHD_E_ARG):
+        _rc(rc, "mhd_load", ctx)
+    return rc
+
+
 def mhd_destroy(ctx):
     lib().mhd_destroy(ctx)
 
@@ -331,14 +374,14 @@ class Solver:
     """Owns one context, its workspace tensor and the stream it runs on."""
 
     def __init__(self, n, precision="fp32", gamma=5.0 / 3.0, nu=0.0, eta=0.0, dt=1e-3, cfl=0.1,
-                 flags=0, device="cuda:0", stream=None):
+                 flags=0, device="cuda:0", stream=None, scheme=MHD_AB2, force=0.0):
         import torch
 
         self.torch = torch
         self.n = int(n)
         codes = {"fp64": MHD_FP64, "fp32": MHD_FP32, "mixed": MHD_MIXED}
         self.precision = codes[precision] if isinstance(precision, str) else int(precision)
-        self.params = make_params(n, self.precision, gamma, nu, eta, dt, cfl, flags)
+        self.params = make_params(n, self.precision, gamma, nu, eta, dt, cfl, flags, scheme, force)
         nbytes = mhd_workspace_bytes(self.params)
         if nbytes == 0:
             raise MHDError(MHD_E_ARG if mhd_supported_size(n, self.precision) else MHD_E_SIZE, "mhd_workspace_bytes")
@@ -407,6 +450,22 @@ class Solver:
     @property
     def step_bytes(self) -> float:
         return mhd_step_bytes(self.ctx)
+
+    @property
+    def checkpoint_bytes(self) -> int:
+        return mhd_checkpoint_bytes(self.ctx)
+
+    def save(self):
+        """A new checkpoint blob (uint8 CUDA tensor view, 256-byte aligned)."""
+        nbytes = self.checkpoint_bytes
+        raw = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        blob = raw[off:off + nbytes]
+        mhd_save(self.ctx, blob)
+        return blob
+
+    def load(self, blob) -> int:
+        return mhd_load(self.ctx, blob)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

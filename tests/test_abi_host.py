@@ -68,13 +68,25 @@ def test_workspace_sizing(M):
 
 
 @pytest.mark.parametrize("field,value", [("gamma", 1.0), ("nu", -1.0), ("eta", -0.1), ("dt", 0.0), ("cfl", 0.0),
-                                         ("dt", float("nan")), ("precision", 7), ("reserved", 1)])
+                                         ("dt", float("nan")), ("precision", 7), ("scheme", 3), ("scheme", -1),
+                                         ("force", float("inf"))])
 def test_invalid_params_rejected(M, field, value):
     p = M.make_params(32)
     setattr(p, field, value)
     assert M.mhd_workspace_bytes(p) == 0
     ctx = ctypes.c_void_p()
     assert M.lib().mhd_init(ctypes.byref(p), ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(ctx)) == M.MHD_E_ARG
+
+
+def test_ensemble_members_take_the_plain_ab2_configuration(M):
+    """Ensemble members run AB2 without the Section V variants."""
+    ok = M.make_params(32)
+    assert M.mhd_ens_workspace_bytes([ok, ok]) > 0
+    for kw in (dict(scheme="rk4"), dict(scheme="pc"), dict(force=0.1), dict(flags=M.MHD_FLAG_KINEMATIC),
+               dict(flags=M.MHD_FLAG_VISC_LAPLACIAN)):
+        bad = M.make_params(32, **kw)
+        assert M.mhd_workspace_bytes(bad) > 0  # fine for a single run
+        assert M.mhd_ens_workspace_bytes([ok, bad]) == 0
 
 
 def test_bad_size_and_workspace(M):

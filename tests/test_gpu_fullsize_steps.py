@@ -1,0 +1,193 @@
+"""Element-wise parity at the benchmark sizes, in the launch configuration
+bench.py times (the wide z-RHS epilogue with the state / history prefetch,
+the wave-mapped row passes, the graph-replayed AB2 step).
+
+* Ten AB2 steps of the 256^3 turbulence workload against the oracle's own
+  256^3 run (tests/golden/oracle_turb256_10steps.json, written by
+  tests/golden/make_golden.py, which calls only the oracle): per-field
+  relative L2 over 1024 sampled grid points and over the low-mode
+  coefficients |k_i| <= 2.  Bars: FP64 1e-11, FP32 1e-5, mixed 1e-3.
+* Ten steps of the 512^3 ABC workload in FP32 and on the mixed path against
+  the FP64 run of the same start (whose z-RHS epilogue takes the narrow,
+  non-prefetching shape, and which the 256^3 record anchors to the oracle):
+  per-field relative L2 over the whole grid, bars 1e-5 and 1e-3.
+* The right-hand side of a varying-density state whose primitive fields are
+  degree-1 trigonometric polynomials (m = rho u, E = P/(gamma-1) + rho|u|^2/2
+  + |B|^2/2): every flux has degree <= 4, so the exact RHS is the same
+  trigonometric polynomial on every grid with n >= 13; the oracle's RHS at
+  16^3 gives its coefficients.  This exercises u = m/rho and the
+  rho-weighted viscous stress with rho != 1 at full size.
+* A well-conditioned state (compressive m, modest background pressure)
+  holds every field of the RHS, R_rho and R_E included, to the flat bars
+  (FP32 1e-5, mixed 1e-3) at sizes the oracle runs directly.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1810_12707_amd import inputs as I
+from tests.gpu_helpers import log, per_field_rel_l2
+from tests.test_gpu_fullsize import eval_points, low_mode_coefficients
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+BAR = {"fp64": 1e-11, "fp32": 1e-5, "mixed": 1e-3}
+
+
+def solver(n, prec, **kw):
+    from paper_1810_12707_amd.mhd import Solver
+
+    return Solver(n, precision=prec, **kw)
+
+
+def load_record():
+    path = os.path.join(HERE, "golden", "oracle_turb256_10steps.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed", "fp64"])
+def test_ten_steps_turb256_against_oracle_record(prec):
+    rec = load_record()
+    n, steps = rec["n"], rec["steps"]
+    log(f"[fullsize record] turb{n} {steps} steps prec={prec}")
+    c = I.config_turb256(n)
+    assert c.dt == rec["dt"] and c.nu == rec["nu"] and c.eta == rec["eta"]
+    S = solver(n, prec, gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt)
+    S.set_state(torch.from_numpy(c.U).to("cuda:0"))
+    del c
+    S.step(1)
+    S.step(steps - 1)  # the Euler start, then graph-replayed AB2 steps
+    out = S.get_state(torch.float64)
+    S.close()
+    idx = torch.tensor(rec["sample_index"], device="cuda:0")
+    got = out.reshape(8, -1)[:, idx].cpu().numpy()
+    ref = np.array(rec["samples"])
+    e_pts = per_field_rel_l2(got, ref)
+    low = low_mode_coefficients(out, rec["low_k"]).cpu().numpy() * n ** 3   # unnormalised, [f][kz][ky][kx]
+    kk = rec["low_k"]
+    e_low = []
+    for f in range(8):
+        rows = np.array(rec["low_modes"][f])
+        kz, ky, kx = rows[:, 0].astype(int), rows[:, 1].astype(int), rows[:, 2].astype(int)
+        want = rows[:, 3] + 1j * rows[:, 4]
+        have = low[f, kz + kk, ky + kk, kx + kk]
+        e_low.append(float(np.linalg.norm(have - want) / np.linalg.norm(want)))
+    log("  sampled points rel L2", ["%.2e" % e for e in e_pts])
+    log("  low modes rel L2     ", ["%.2e" % e for e in e_low])
+    assert max(e_pts) <= BAR[prec]
+    assert max(e_low) <= BAR[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_ten_steps_abc512_against_fp64_run(prec):
+    n = 512
+    log(f"[fullsize vs fp64] abc{n} 10 steps prec={prec}")
+    c = I.config_dynamo512(n)
+    U = torch.from_numpy(c.U).to("cuda:0")
+    kw = dict(gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt)
+    del c
+    D = solver(n, "fp64", **kw)
+    D.set_state(U)
+    D.step(10)
+    ref = D.get_state(torch.float64)
+    D.close()
+    del D
+    torch.cuda.empty_cache()
+    S = solver(n, prec, **kw)
+    S.set_state(U)
+    del U
+    S.step(10)
+    got = S.get_state(torch.float64)
+    S.close()
+    errs = [float(torch.linalg.vector_norm(got[f] - ref[f]) / torch.linalg.vector_norm(ref[f])) for f in range(8)]
+    log("  per-field rel L2", ["%.2e" % e for e in errs])
+    assert max(errs) <= BAR[prec]
+    del got, ref
+    torch.cuda.empty_cache()
+
+
+def varying_density_rhs(n0, ts, gamma, nu, eta, kmax=4):
+    """The oracle's RHS of the trigonometric state at n0^3: its Fourier
+    coefficients (1/n0^3 normalisation) on |k_i| <= kmax, after checking that
+    nothing lies outside."""
+    z, y, x = I.grid(n0)
+    U0 = ts.conserved(z, y, x, gamma)
+    R0 = O.rhs(U0, gamma, nu, eta)
+    F = np.fft.fftn(R0, axes=(-3, -2, -1)) / n0 ** 3
+    k = np.fft.fftfreq(n0, 1.0 / n0).astype(int)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    keep = (np.abs(kx) <= kmax) & (np.abs(ky) <= kmax) & (np.abs(kz) <= kmax)
+    assert np.max(np.abs(F[:, ~keep])) <= 1e-12 * np.max(np.abs(F))
+    return F, (kz, ky, kx), keep
+
+
+@pytest.mark.parametrize("n,prec", [(256, "fp64"), (256, "fp32"), (256, "mixed"), (512, "fp32"), (512, "mixed")])
+def test_rhs_exact_varying_density(n, prec):
+    log(f"[fullsize rhs, varying rho] n={n} prec={prec}")
+    gamma, nu, eta = 5.0 / 3.0, 2e-3, 3e-3
+    ts = I.trig_state(3)
+    F, (kz, ky, kx), keep = varying_density_rhs(16, ts, gamma, nu, eta)
+    dt_ = torch.float64 if prec == "fp64" else torch.float32
+    xs = torch.arange(n, device="cuda:0", dtype=torch.float64) * (2 * np.pi / n)
+    Un = torch.empty((8, n, n, n), dtype=dt_, device="cuda:0")
+    for zi in range(0, n, 64):  # build in slabs of 64 planes (FP64 temporaries)
+        z = xs[zi:zi + 64, None, None]
+        Un[:, zi:zi + 64] = ts.conserved(z, xs[None, :, None], xs[None, None, :], gamma, xp=torch).to(dt_)
+    S = solver(n, prec, gamma=gamma, nu=nu, eta=eta)
+    out = S.rhs(Un)
+    del Un
+    S.close()
+    if prec == "fp64":
+        kvec = np.stack([kx[keep], ky[keep], kz[keep]], axis=1).astype(np.float64)
+        coef = F[:, keep]
+        rng = np.random.default_rng(9)
+        pts = rng.integers(0, n, size=(4096, 3))
+        pt = torch.from_numpy(pts).to("cuda:0")
+        got = out[:, pt[:, 0], pt[:, 1], pt[:, 2]].double().cpu().numpy()
+        ref = eval_points(coef, kvec, pts.astype(np.float64), n)
+        errs = per_field_rel_l2(got, ref)
+        log("  sampled points rel L2", ["%.2e" % e for e in errs])
+        assert max(errs) <= 1e-11
+        return
+    idx = np.r_[-4:5] % 16
+    exact = F[:, idx[:, None, None], idx[None, :, None], idx[None, None, :]]   # [f][kz][ky][kx]
+    got = low_mode_coefficients(out, 4).cpu().numpy()
+    K = (n - 1) // 3
+    # FP32 rounding of the fluxes (|F^E| <= ~2) is white over all modes; the
+    # divergence multiplies mode k by |k| <= sqrt(3) K
+    noise = 1.2e-7 * 2.0 * np.sqrt(3.0) * K
+    if prec == "mixed":
+        noise *= 256.0
+    for f in range(8):
+        e = np.linalg.norm(got[f] - exact[f]) / np.linalg.norm(exact[f])
+        tot = float(torch.linalg.vector_norm(out[f].double())) ** 2 / n ** 3
+        low = float(np.sum(np.abs(got[f]) ** 2))
+        rest = np.sqrt(max(tot - low, 0.0))
+        log(f"  field {I.FIELD_NAMES[f]}: low modes rel {e:.3e}; rms outside {rest:.3e} (bound {noise:.1e})")
+        assert e <= BAR[prec], (f, e)
+        assert rest <= noise, (f, rest, noise)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("n", [16, 32, 48])
+def test_rhs_well_conditioned_flat_bars(n, prec):
+    log(f"[rhs, well conditioned] n={n} prec={prec}")
+    gamma, nu, eta = 5.0 / 3.0, 3e-3, 5e-3
+    U = I.compressive_state(n, 100 + n, gamma)
+    ref = O.rhs(U, gamma, nu, eta)
+    # the state is well conditioned: rounding it to FP32 moves the oracle's RHS by far less than the bar
+    sens = per_field_rel_l2(O.rhs(U.astype(np.float32).astype(np.float64), gamma, nu, eta), ref)
+    assert max(sens) <= 1e-6
+    S = solver(n, prec, gamma=gamma, nu=nu, eta=eta)
+    got = S.rhs(torch.from_numpy(U).to(device="cuda:0", dtype=torch.float32)).double().cpu().numpy()
+    S.close()
+    errs = per_field_rel_l2(got, ref)
+    log("  err", ["%.2e" % e for e in errs])
+    assert max(errs) <= BAR[prec]
