@@ -169,6 +169,25 @@ int mhd_get_state(mhd_ctx* ctx, void* d_fields, int32_t dtype);
  * they may not overlap.  MHD_E_ARG for a null pointer or a bad dtype. */
 int mhd_rhs(mhd_ctx* ctx, const void* d_fields_in, void* d_rhs_out, int32_t dtype);
 
+/* Allocation-free right-hand side, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same result as mhd_init + mhd_rhs with parameters p
+ * (bit for bit: the same kernels and launch geometry), but the workspace is
+ * a file-scope device array of the library (64 MiB; each GPU holds its own
+ * copy until the process ends) and the context lives on the caller's stack,
+ * so nothing is allocated on the device or the host.  d_fields_in /
+ * d_rhs_out: caller-owned [8][n][n][n] arrays of element type dtype, on the
+ * current device; the work is enqueued on hip_stream (NULL = default stream)
+ * after one synchronous upload of the twiddle table.  Sizes whose workspace
+ * exceeds 64 MiB (mhd_workspace_bytes(p) > 64 MiB: n <= 64 fits in every
+ * precision) return MHD_E_WORKSPACE.  Every call on a GPU shares that GPU's
+ * array and leaves its contents behind; nothing in it needs to start at zero
+ * (every array the right-hand side reads is written earlier in the same
+ * call).  Calls that overlap on one GPU (other streams, other host threads)
+ * race on the array and must be serialised by the caller. */
+int mhd_rhs_noalloc(const mhd_params* p, const void* d_fields_in, void* d_rhs_out, int32_t dtype,
+                    void* hip_stream);
+
 /* Advances the state by nsteps >= 0 steps of the Adams-Bashforth scheme
  * (Sections II and IV; second order, fixed dt):
  * U^{n+1} = U^n + dt (3/2 R^n - 1/2 R^{n-1}); the first step after

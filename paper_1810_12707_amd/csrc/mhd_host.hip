@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -982,16 +983,10 @@ int validate_member(const mhd_params* p) {
 
 }  // namespace
 
-static int ctx_create(const mhd_params* p, void* d_workspace, size_t ws_bytes, hipStream_t stream, mhd_ctx** out) {
-  if (!out) return MHD_E_ARG;
-  *out = nullptr;
-  int v = validate(p);
-  if (v != MHD_OK) return v;
-  const size_t need = mhd_workspace_bytes(p);
-  if (!d_workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
-    return MHD_E_WORKSPACE;
-  mhd_ctx* c = new (std::nothrow) mhd_ctx();
-  if (!c) return MHD_E_ARG;
+// Sets up a context in place (no allocation): parameters, layout, launch
+// geometry and the twiddle table, uploaded through a host buffer on the stack
+// (synchronously).  The workspace must have been checked by the caller.
+static int ctx_setup(mhd_ctx* c, const mhd_params* p, void* d_workspace, size_t ws_bytes, hipStream_t stream) {
   c->p = *p;
   c->g = make_geo(p->n);
   const size_t ts = is_fp32(p->precision) ? sizeof(float) : sizeof(double);
@@ -1004,58 +999,62 @@ static int ctx_create(const mhd_params* p, void* d_workspace, size_t ws_bytes, h
   c->step = 0;
   c->t = 0.0;
   const void* kv = kern_for(c);
-  if (!kv) {
-    delete c;
-    return MHD_E_SIZE;
+  if (!kv) return MHD_E_SIZE;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess || c->num_cus <= 0) return MHD_E_HIP;
+  const bool f32 = is_fp32(p->precision);
+  for (int m = 0; m < 5; ++m) {
+    const int occ = f32 ? static_cast<const Kern<float>*>(kv)->row_occupancy(m)
+                        : static_cast<const Kern<double>*>(kv)->row_occupancy(m);
+    c->row_blocks[m] = occ * c->num_cus;
   }
-  {
-    int dev = 0;
-    hipError_t e0 = hipGetDevice(&dev);
-    if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e0 != hipSuccess || c->num_cus <= 0) {
-      delete c;
-      return MHD_E_HIP;
-    }
-    for (int m = 0; m < 5; ++m) {
-      const int occ = is_fp32(p->precision) ? static_cast<const Kern<float>*>(kv)->row_occupancy(m)
-                                            : static_cast<const Kern<double>*>(kv)->row_occupancy(m);
-      c->row_blocks[m] = occ * c->num_cus;
-    }
-    const bool f32 = is_fp32(p->precision);
-    const int cocc[3] = {f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(-1, 1)
-                             : static_cast<const Kern<double>*>(kv)->col_occupancy(-1, 1),
-                         f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 1)
-                             : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 1),
-                         f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 3)
-                             : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 3)};
-    for (int m = 0; m < 3; ++m) c->col_blocks[m] = cocc[m] * c->num_cus;
-  }
+  const int cocc[3] = {f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(-1, 1)
+                           : static_cast<const Kern<double>*>(kv)->col_occupancy(-1, 1),
+                       f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 1)
+                           : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 1),
+                       f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 3)
+                           : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 3)};
+  for (int m = 0; m < 3; ++m) c->col_blocks[m] = cocc[m] * c->num_cus;
   // twiddles exp(-2 pi i j / n) in FP64, rounded once to the working precision
   const int n = p->n;
   const double two_pi = 6.28318530717958647692528676655900577;
-  hipError_t e;
-  if (is_fp32(p->precision)) {
-    float* h = new float[2 * (size_t)n];
-    for (int j = 0; j < n; ++j) {
-      h[2 * j] = (float)std::cos(two_pi * j / n);
-      h[2 * j + 1] = (float)-std::sin(two_pi * j / n);
-    }
-    e = hipMemcpyAsync(c->ws + c->L.tw, h, 2 * (size_t)n * sizeof(float), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    delete[] h;
-  } else {
-    double* h = new double[2 * (size_t)n];
-    for (int j = 0; j < n; ++j) {
-      h[2 * j] = std::cos(two_pi * j / n);
-      h[2 * j + 1] = -std::sin(two_pi * j / n);
-    }
-    e = hipMemcpyAsync(c->ws + c->L.tw, h, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    delete[] h;
+  double h64[2 * 1024];
+  float h32[2 * 1024];
+  for (int j = 0; j < n; ++j) {
+    const double cr = std::cos(two_pi * j / n), ci = -std::sin(two_pi * j / n);
+    h64[2 * j] = cr;
+    h64[2 * j + 1] = ci;
+    h32[2 * j] = (float)cr;
+    h32[2 * j + 1] = (float)ci;
   }
-  if (e != hipSuccess) {
+  const void* src = f32 ? static_cast<const void*>(h32) : static_cast<const void*>(h64);
+  e = hipMemcpyAsync(c->ws + c->L.tw, src, 2 * (size_t)n * ts, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host buffer dies with this frame
+  return e == hipSuccess ? MHD_OK : MHD_E_HIP;
+}
+
+static int ctx_check(const mhd_params* p, void* d_workspace, size_t ws_bytes) {
+  const int v = validate(p);
+  if (v != MHD_OK) return v;
+  const size_t need = mhd_workspace_bytes(p);
+  if (!d_workspace || ws_bytes < need || (reinterpret_cast<uintptr_t>(d_workspace) & 255u) != 0)
+    return MHD_E_WORKSPACE;
+  return MHD_OK;
+}
+
+static int ctx_create(const mhd_params* p, void* d_workspace, size_t ws_bytes, hipStream_t stream, mhd_ctx** out) {
+  if (!out) return MHD_E_ARG;
+  *out = nullptr;
+  int rc = ctx_check(p, d_workspace, ws_bytes);
+  if (rc != MHD_OK) return rc;
+  mhd_ctx* c = new (std::nothrow) mhd_ctx();
+  if (!c) return MHD_E_ARG;
+  rc = ctx_setup(c, p, d_workspace, ws_bytes, stream);
+  if (rc != MHD_OK) {
     delete c;
-    return MHD_E_HIP;
+    return rc;
   }
   *out = c;
   return MHD_OK;
@@ -1179,6 +1178,33 @@ static void blob_hash(mhd_ctx* c, const char* blob, size_t bytes, unsigned long 
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_blob_hash, dim3((unsigned)blocks), dim3(kThreads), 0, c->stream,
                      reinterpret_cast<const uint64_t*>(blob), words, (int64_t)kCkptSumWord, out);
+}
+
+// Device scratch of mhd_rhs_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel: scratch_address resolves each
+// device's copy once, with that device current, and every later use goes
+// through that address.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+
+static int scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return MHD_E_HIP;
+  if (dev < 0 || dev >= kMaxDevices) return MHD_E_ARG;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return MHD_E_HIP;
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return MHD_OK;
 }
 
 // ------------------------------------------------------------------ ensembles
@@ -1475,6 +1501,22 @@ int mhd_rhs(mhd_ctx* c, const void* d_in, void* d_out, int32_t dtype) {
     e.inverse_real(e.trhs(), 8, d_out, dtype);
     return check_launch(c, "mhd_rhs");
   });
+}
+
+int mhd_rhs_noalloc(const mhd_params* p, const void* d_in, void* d_out, int32_t dtype, void* hip_stream) {
+  if (!p || !d_in || !d_out || !dtype_ok(dtype)) return MHD_E_ARG;
+  const int v = validate(p);
+  if (v != MHD_OK) return v;
+  if (mhd_workspace_bytes(p) > kScratchBytes) return MHD_E_WORKSPACE;  // beyond the static scratch
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc != MHD_OK) return rc;
+  // a context on the stack over the scratch: nothing is allocated, on the
+  // device or the host (its string and vectors stay empty)
+  mhd_ctx c;
+  rc = ctx_setup(&c, p, ws, kScratchBytes, static_cast<hipStream_t>(hip_stream));
+  if (rc != MHD_OK) return rc;
+  return mhd_rhs(&c, d_in, d_out, dtype);  // every launch is enqueued (arguments copied) when this returns
 }
 
 int mhd_step(mhd_ctx* c, int32_t nsteps) {

@@ -31,7 +31,7 @@ EXPORTED = (
     "mhd_supported_size", "mhd_workspace_bytes", "mhd_init", "mhd_set_state", "mhd_get_state",
     "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_spectrum_pitch", "mhd_destroy",
     "mhd_status_string", "mhd_last_error", "mhd_profile", "mhd_profile_read", "mhd_step_bytes",
-    "mhd_checkpoint_bytes", "mhd_save", "mhd_load", "mhd_bench_copy",
+    "mhd_checkpoint_bytes", "mhd_save", "mhd_load", "mhd_bench_copy", "mhd_rhs_noalloc",
     "mhd_ens_workspace_bytes", "mhd_ens_init", "mhd_ens_set_state", "mhd_ens_get_state", "mhd_ens_step",
     "mhd_ens_diagnostics", "mhd_ens_num_groups", "mhd_ens_group_info", "mhd_ens_step_bytes", "mhd_ens_destroy",
     "mhd_ens_last_error",
@@ -117,6 +117,8 @@ def lib() -> ctypes.CDLL:
         L.mhd_checkpoint_bytes.restype = ctypes.c_size_t
         L.mhd_save.argtypes = [vp, vp]
         L.mhd_bench_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
+        L.mhd_rhs_noalloc.argtypes = [P, vp, vp, ctypes.c_int32, vp]
+        L.mhd_rhs_noalloc.restype = ctypes.c_int
         L.mhd_bench_copy.restype = ctypes.c_int
         L.mhd_load.argtypes = [vp, vp]
         i32 = ctypes.c_int32
@@ -222,6 +224,16 @@ def mhd_rhs(ctx, fields_in, rhs_out):
         raise TypeError("fields_in and rhs_out must share a dtype")
     _rc(lib().mhd_rhs(ctx, ctypes.c_void_p(fields_in.data_ptr()), ctypes.c_void_p(rhs_out.data_ptr()),
                       _dtype_code(fields_in)), "mhd_rhs", ctx)
+
+
+def mhd_rhs_noalloc(p: mhd_params, fields_in, rhs_out, stream_handle: int) -> int:
+    """Status of the allocation-free right-hand side (MHD_OK, MHD_E_WORKSPACE
+    beyond its 64 MiB scratch, ...)."""
+    if fields_in.dtype != rhs_out.dtype:
+        raise TypeError("fields_in and rhs_out must share a dtype")
+    return int(lib().mhd_rhs_noalloc(ctypes.byref(p), ctypes.c_void_p(fields_in.data_ptr()),
+                                     ctypes.c_void_p(rhs_out.data_ptr()), _dtype_code(fields_in),
+                                     ctypes.c_void_p(stream_handle)))
 
 
 def mhd_step(ctx, nsteps: int):
