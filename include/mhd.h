@@ -208,6 +208,27 @@ int mhd_step(mhd_ctx* ctx, int32_t nsteps);
  * either way.  MHD_E_STATE if no state is set. */
 int mhd_diagnostics(mhd_ctx* ctx, mhd_diag* h_out);
 
+/* Tracer particles (Section VI): passive particles sprinkled in the box,
+ * moved by the magnetic field of the grid.  d_pos, d_vel: caller-owned FP64
+ * device arrays [np][3] of (x, y, z) components; positions are taken modulo
+ * the period 2 pi.  Grid fields are interpolated to a particle by
+ * cloud-in-cell weights (Section VI's eight-corner volume weighting,
+ * normalised by the cell volume: the trilinear interpolant; the paper's
+ * extra factor dt in those weights is dropped).  Both calls use the current
+ * state (synthesised to real space in the workspace's scratch) and enqueue
+ * on the context's stream.
+ * mhd_tracers_velocity: d_vel = the grid velocity u = m/rho interpolated at
+ *   d_pos (the tracers' initial velocity, Section VI).
+ * mhd_tracers_push: nsteps Boris steps of length dt with q = M = 1:
+ *   t = B_p dt/2, s = 2t/(1 + |t|^2), v' = v + v x t, v <- v + v' x s,
+ *   x <- x + v dt, wrapped into [0, 2 pi); B_p is the field interpolated at
+ *   each step's start position.  The field is the current state's, held fixed
+ *   over the call; interleave with mhd_step to follow an evolving flow.
+ * MHD_E_STATE if no state is set; MHD_E_ARG for null arrays with np > 0,
+ * np < 0, nsteps < 0 or a non-finite dt. */
+int mhd_tracers_velocity(mhd_ctx* ctx, const double* d_pos, double* d_vel, int64_t np);
+int mhd_tracers_push(mhd_ctx* ctx, double* d_pos, double* d_vel, int64_t np, double dt, int32_t nsteps);
+
 /* Checkpoint/restart of the multistep state.  The AB2 scheme (Sections II
  * and IV) carries the previous right-hand side R^{n-1} besides U^n, so a
  * restart needs both: a checkpoint blob holds a 256-byte header (format

@@ -85,6 +85,16 @@ int orc_run(const orc_params* p, double* U, int32_t nsteps);
 /* Diagnostics of the state U^ = D F U (see the ORC_* indices). */
 int orc_diag(const orc_params* p, const double* U, double* out);
 
+/* Tracer particles (Section VI).  Positions pos[np][3] = (x, y, z) in
+ * [0, 2 pi) (any real value is taken modulo the period).
+ * orc_cic: cloud-in-cell interpolation of the real fields f[nc][n^3] at the
+ *   positions into out[np][nc] (the trilinear interpolant of the grid values).
+ * orc_tracer_push: nsteps Boris steps (q = M = 1) in the magnetic field
+ *   B[3][n^3], interpolated by cloud-in-cell at each step's start position;
+ *   positions advance by v dt and wrap into [0, 2 pi). */
+int orc_cic(int32_t n, const double* f, int32_t nc, const double* pos, int64_t np, double* out);
+int orc_tracer_push(int32_t n, const double* B, double* pos, double* vel, int64_t np, double dt, int32_t nsteps);
+
 /* Neumaier compensated sum (exposed so tests can pin it against math.fsum). */
 double orc_neumaier_sum(const double* x, int64_t n);
 

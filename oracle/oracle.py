@@ -68,6 +68,10 @@ def lib():
         L.orc_neumaier_sum.restype = ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int32
         L.orc_set_num_threads.argtypes = [ctypes.c_int32]
+        L.orc_cic.argtypes = [ctypes.c_int32, dp, ctypes.c_int32, dp, ctypes.c_int64, dp]
+        L.orc_cic.restype = ctypes.c_int
+        L.orc_tracer_push.argtypes = [ctypes.c_int32, dp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32]
+        L.orc_tracer_push.restype = ctypes.c_int
         L.orc_set_num_threads.restype = None
         for name in ("orc_fft1d", "orc_fft3d", "orc_project", "orc_rhs", "orc_run", "orc_diag"):
             getattr(L, name).restype = ctypes.c_int
@@ -141,6 +145,27 @@ def diag(U, gamma=5.0 / 3.0, nu=0.0, eta=0.0, cfl=0.1) -> dict:
     p = _params(U.shape[1], gamma, nu, eta, 0.0, cfl)
     _check(lib().orc_diag(ctypes.byref(p), _ptr(U), _ptr(out)), "diag")
     return dict(zip(DIAG_NAMES, out.tolist()))
+
+
+def cic(f, pos) -> np.ndarray:
+    """Cloud-in-cell values (np, nc) of the real fields f (nc, n, n, n) at
+    positions pos (np, 3) = (x, y, z)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    nc, n = f.shape[0], f.shape[1]
+    out = np.empty((pos.shape[0], nc))
+    _check(lib().orc_cic(n, _ptr(f), nc, _ptr(pos), pos.shape[0], _ptr(out)), "cic")
+    return out
+
+
+def tracer_push(B, pos, vel, dt: float, nsteps: int):
+    """nsteps Boris steps in the field B (3, n, n, n); returns (pos, vel)."""
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    pos = np.array(pos, dtype=np.float64, order="C", copy=True)
+    vel = np.array(vel, dtype=np.float64, order="C", copy=True)
+    _check(lib().orc_tracer_push(B.shape[1], _ptr(B), _ptr(pos), _ptr(vel), pos.shape[0], float(dt), int(nsteps)),
+           "tracer_push")
+    return pos, vel
 
 
 def neumaier_sum(x) -> float:

@@ -558,6 +558,80 @@ int orc_run(const orc_params* p, double* U, int32_t nsteps) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Tracer particles (Section VI): cloud-in-cell interpolation of grid fields  */
+/* to particle positions and the Boris push in the magnetic field.            */
+/* ------------------------------------------------------------------------- */
+
+/* Grid point j of an axis sits at x_j = 2 pi j / n.  A particle at x lies in
+ * the cell with lower corner i = floor(x / dx) (periodic), at fraction
+ * f = x / dx - i; each of the eight corners weighs the product over the axes
+ * of f (upper corner) or 1 - f (lower corner): the volume of the opposite
+ * sub-box, normalised by the cell volume. */
+static void cic_setup(int n, double x, int* i0, int* i1, double* f) {
+    const double dx = TWO_PI / n;
+    double s = x / dx;
+    double fl = floor(s);
+    *f = s - fl;
+    long i = (long)fl % n;
+    if (i < 0) i += n;
+    *i0 = (int)i;
+    *i1 = (int)((i + 1) % n);
+}
+
+int orc_cic(int32_t n, const double* f, int32_t nc, const double* pos, int64_t np, double* out) {
+    if (n < 1 || !f || nc < 1 || !pos || np < 0 || !out) return -1;
+    const long n3 = (long)n * n * n;
+    for (int64_t p = 0; p < np; ++p) {
+        int ix0, ix1, iy0, iy1, iz0, iz1;
+        double fx, fy, fz;
+        cic_setup(n, pos[3 * p + 0], &ix0, &ix1, &fx);
+        cic_setup(n, pos[3 * p + 1], &iy0, &iy1, &fy);
+        cic_setup(n, pos[3 * p + 2], &iz0, &iz1, &fz);
+        const int ix[2] = {ix0, ix1}, iy[2] = {iy0, iy1}, iz[2] = {iz0, iz1};
+        const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+        for (int c = 0; c < nc; ++c) {
+            double acc = 0.0;
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int d = 0; d < 2; ++d)
+                        acc += wz[a] * wy[b] * wx[d] * f[c * n3 + ((long)iz[a] * n + iy[b]) * n + ix[d]];
+            out[p * nc + c] = acc;
+        }
+    }
+    return 0;
+}
+
+/* Boris push with q = M = 1 (Section VI, Eqs. for t, s, v_d, v and x):
+ * t = B dt / 2, s = 2 t / (1 + |t|^2), v' = v + v x t, v+ = v + v' x s,
+ * x+ = x + v+ dt, wrapped into [0, 2 pi).  B is interpolated at the particle's
+ * position at the start of each step. */
+int orc_tracer_push(int32_t n, const double* B, double* pos, double* vel, int64_t np, double dt, int32_t nsteps) {
+    if (n < 1 || !B || !pos || !vel || np < 0 || nsteps < 0) return -1;
+    for (int s = 0; s < nsteps; ++s) {
+        for (int64_t p = 0; p < np; ++p) {
+            double Bp[3];
+            orc_cic(n, B, 3, pos + 3 * p, 1, Bp);
+            double t[3] = {0.5 * dt * Bp[0], 0.5 * dt * Bp[1], 0.5 * dt * Bp[2]};
+            const double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+            double sv[3] = {2.0 * t[0] / (1.0 + t2), 2.0 * t[1] / (1.0 + t2), 2.0 * t[2] / (1.0 + t2)};
+            double* v = vel + 3 * p;
+            double vd[3] = {v[0] + (v[1] * t[2] - v[2] * t[1]), v[1] + (v[2] * t[0] - v[0] * t[2]),
+                            v[2] + (v[0] * t[1] - v[1] * t[0])};
+            double vn[3] = {v[0] + (vd[1] * sv[2] - vd[2] * sv[1]), v[1] + (vd[2] * sv[0] - vd[0] * sv[2]),
+                            v[2] + (vd[0] * sv[1] - vd[1] * sv[0])};
+            for (int c = 0; c < 3; ++c) {
+                v[c] = vn[c];
+                double x = pos[3 * p + c] + vn[c] * dt;
+                x = fmod(x, TWO_PI);
+                if (x < 0) x += TWO_PI;
+                pos[3 * p + c] = x;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Diagnostics (volume means, Neumaier sums).                                 */
 /* ------------------------------------------------------------------------- */
 

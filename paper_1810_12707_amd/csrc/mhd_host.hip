@@ -250,6 +250,111 @@ __global__ void __launch_bounds__(kThreads) k_combine(T* __restrict__ u, const T
   }
 }
 
+// ------------------------------------------------------------------ tracers
+// Tracer particles of Section VI.  Positions and velocities are FP64 device
+// arrays [np][3] (x, y, z); the grid fields are real-space fields in the
+// working precision, [nf][n^3] with x fastest; interpolation and push are FP64.
+//
+// Cloud-in-cell: a particle at x lies in the cell whose lower corner is grid
+// point i = floor(x / dx) (periodic, dx = 2 pi / n), at fraction f = x/dx - i
+// of the cell; corner i weighs 1 - f and corner i + 1 weighs f per axis, and a
+// corner's weight is the product over the axes: the volume of the opposite
+// sub-box over the cell volume (trilinear interpolation).
+struct CicAxis {
+  int i0, i1;
+  double w0, w1;
+};
+__device__ __forceinline__ CicAxis cic_axis(int n, double x) {
+  const double dx = 6.28318530717958647692528676655900577 / n;
+  const double s = x / dx;
+  const double fl = floor(s);
+  long long i = (long long)fl % n;
+  if (i < 0) i += n;
+  CicAxis a;
+  a.i0 = (int)i;
+  a.i1 = (int)((i + 1) % n);
+  a.w1 = s - fl;
+  a.w0 = 1.0 - a.w1;
+  return a;
+}
+
+// Interpolated value of `nc` fields (field c at base + c * n^3) at p; the
+// callback receives the eight corner indices and weights.
+template <typename F>
+__device__ __forceinline__ void cic_corners(int n, const double* p, F&& visit) {
+  const CicAxis ax = cic_axis(n, p[0]), ay = cic_axis(n, p[1]), az = cic_axis(n, p[2]);
+  const int xi[2] = {ax.i0, ax.i1}, yi[2] = {ay.i0, ay.i1}, zi[2] = {az.i0, az.i1};
+  const double xw[2] = {ax.w0, ax.w1}, yw[2] = {ay.w0, ay.w1}, zw[2] = {az.w0, az.w1};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+        visit(((int64_t)zi[a] * n + yi[b]) * n + xi[d], zw[a] * yw[b] * xw[d]);
+}
+
+// Initial tracer velocity: the grid velocity u = m / rho (at the grid points,
+// from the real-space rho and m: fields 0..3 of `f`) interpolated by CIC.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_tracer_velocity(const T* __restrict__ f, int n,
+                                                             const double* __restrict__ pos, double* __restrict__ vel,
+                                                             int64_t np) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= np) return;
+  const int64_t n3 = (int64_t)n * n * n;
+  double acc[3] = {0.0, 0.0, 0.0};
+  cic_corners(n, pos + 3 * p, [&](int64_t g, double w) {
+    const double rho = double(f[g]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) acc[c] += w * (double(f[(1 + c) * n3 + g]) / rho);
+  });
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vel[3 * p + c] = acc[c];
+}
+
+// nsteps Boris steps (q = M = 1) in the magnetic field B (fields 0..2 of `b`):
+// t = B dt / 2, s = 2 t / (1 + |t|^2), v' = v + v x t, v <- v + v' x s,
+// x <- x + v dt wrapped into [0, 2 pi); B is interpolated at each step's
+// start position.  One thread per particle.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_tracer_push(const T* __restrict__ b, int n, double* __restrict__ pos,
+                                                         double* __restrict__ vel, int64_t np, double dt,
+                                                         int nsteps) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= np) return;
+  const double two_pi = 6.28318530717958647692528676655900577;
+  const int64_t n3 = (int64_t)n * n * n;
+  double x[3] = {pos[3 * p], pos[3 * p + 1], pos[3 * p + 2]};
+  double v[3] = {vel[3 * p], vel[3 * p + 1], vel[3 * p + 2]};
+  for (int s = 0; s < nsteps; ++s) {
+    double B[3] = {0.0, 0.0, 0.0};
+    cic_corners(n, x, [&](int64_t g, double w) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) B[c] += w * double(b[c * n3 + g]);
+    });
+    const double t[3] = {0.5 * dt * B[0], 0.5 * dt * B[1], 0.5 * dt * B[2]};
+    const double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    const double sv[3] = {2.0 * t[0] / (1.0 + t2), 2.0 * t[1] / (1.0 + t2), 2.0 * t[2] / (1.0 + t2)};
+    const double vd[3] = {v[0] + (v[1] * t[2] - v[2] * t[1]), v[1] + (v[2] * t[0] - v[0] * t[2]),
+                          v[2] + (v[0] * t[1] - v[1] * t[0])};
+    const double vn[3] = {v[0] + (vd[1] * sv[2] - vd[2] * sv[1]), v[1] + (vd[2] * sv[0] - vd[0] * sv[2]),
+                          v[2] + (vd[0] * sv[1] - vd[1] * sv[0])};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      v[c] = vn[c];
+      double xc = fmod(x[c] + vn[c] * dt, two_pi);
+      if (xc < 0) xc += two_pi;
+      x[c] = xc;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    pos[3 * p + c] = x[c];
+    vel[3 * p + c] = v[c];
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz, Geo g,
@@ -294,20 +399,15 @@ k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restr
 }
 
 // Streaming copy of n 16-byte words (the benchmark's practical HBM
-// ceiling): a grid-stride loop with four independent 16-byte loads in flight
-// per thread before their stores.
+// ceiling): one 16-byte load and store per thread and iteration of a
+// grid-stride loop over four resident workgroups per CU.  Measured on 1 GiB
+// against unrolled (four and eight loads in flight), nontemporal and
+// contiguous-chunk variants and more workgroups per CU, this plain form was
+// the fastest (5.66 TB/s read + write; hipMemcpy 5.08).
 __global__ void __launch_bounds__(kThreads) k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                          int64_t n) {
   const int64_t stride = (int64_t)gridDim.x * kThreads;
-  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  for (; i + 3 * stride < n; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
-  }
-  for (; i < n; i += stride) dst[i] = src[i];
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
@@ -1618,6 +1718,37 @@ int mhd_load(mhd_ctx* c, const void* d_blob) {
 
 int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) { return ctx_diag(c, h); }
 
+// Tracers: the real-space fields they need are synthesised from the state
+// into the I_y scratch from slot 4 on (at most four fields: 4 n^3 words, at
+// most 6 of the 12 free slots), behind the inverse transform's own slots 0-3.
+int mhd_tracers_velocity(mhd_ctx* c, const double* d_pos, double* d_vel, int64_t np) {
+  if (!c || np < 0 || (np > 0 && (!d_pos || !d_vel))) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  if (np == 0) return MHD_OK;
+  return with_engine(c, [&](auto& e) {
+    using T = std::remove_pointer_t<decltype(e.state())>;
+    T* real = e.iy(4);
+    e.inverse_real(e.state(), 4, real, is_fp32(c->p.precision) ? MHD_FP32 : MHD_FP64);  // rho, m
+    hipLaunchKernelGGL((k_tracer_velocity<T>), dim3((unsigned)((np + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       c->stream, real, c->g.n, d_pos, d_vel, np);
+    return check_launch(c, "mhd_tracers_velocity");
+  });
+}
+
+int mhd_tracers_push(mhd_ctx* c, double* d_pos, double* d_vel, int64_t np, double dt, int32_t nsteps) {
+  if (!c || np < 0 || nsteps < 0 || !std::isfinite(dt) || (np > 0 && (!d_pos || !d_vel))) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  if (np == 0 || nsteps == 0) return MHD_OK;
+  return with_engine(c, [&](auto& e) {
+    using T = std::remove_pointer_t<decltype(e.state())>;
+    T* real = e.iy(4);
+    e.inverse_real(e.spec_field(e.state(), 4), 3, real, is_fp32(c->p.precision) ? MHD_FP32 : MHD_FP64);  // B
+    hipLaunchKernelGGL((k_tracer_push<T>), dim3((unsigned)((np + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                       c->stream, real, c->g.n, d_pos, d_vel, np, dt, (int)nsteps);
+    return check_launch(c, "mhd_tracers_push");
+  });
+}
+
 int mhd_fft3d(mhd_ctx* c, int32_t dir, const void* d_in, void* d_out) {
   if (!c || !d_in || !d_out || (dir != 1 && dir != -1)) return MHD_E_ARG;
   return with_engine(c, [&](auto& e) {
@@ -1720,7 +1851,7 @@ int mhd_bench_copy(const void* d_src, void* d_dst, size_t bytes, void* hip_strea
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     return MHD_E_HIP;
   const int64_t words = (int64_t)(bytes / 16);
-  int64_t blocks = (int64_t)cus * 8;  // eight resident 256-thread workgroups per CU
+  int64_t blocks = (int64_t)cus * 4;  // four 256-thread workgroups per CU
   const int64_t need = (words + kThreads - 1) / kThreads;
   if (blocks > need) blocks = need < 1 ? 1 : need;
   hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(kThreads), 0, static_cast<hipStream_t>(hip_stream),

@@ -32,6 +32,7 @@ EXPORTED = (
     "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_spectrum_pitch", "mhd_destroy",
     "mhd_status_string", "mhd_last_error", "mhd_profile", "mhd_profile_read", "mhd_step_bytes",
     "mhd_checkpoint_bytes", "mhd_save", "mhd_load", "mhd_bench_copy", "mhd_rhs_noalloc",
+    "mhd_tracers_velocity", "mhd_tracers_push",
     "mhd_ens_workspace_bytes", "mhd_ens_init", "mhd_ens_set_state", "mhd_ens_get_state", "mhd_ens_step",
     "mhd_ens_diagnostics", "mhd_ens_num_groups", "mhd_ens_group_info", "mhd_ens_step_bytes", "mhd_ens_destroy",
     "mhd_ens_last_error",
@@ -118,6 +119,10 @@ def lib() -> ctypes.CDLL:
         L.mhd_save.argtypes = [vp, vp]
         L.mhd_bench_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.mhd_rhs_noalloc.argtypes = [P, vp, vp, ctypes.c_int32, vp]
+        L.mhd_tracers_velocity.argtypes = [vp, vp, vp, ctypes.c_int64]
+        L.mhd_tracers_velocity.restype = ctypes.c_int
+        L.mhd_tracers_push.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32]
+        L.mhd_tracers_push.restype = ctypes.c_int
         L.mhd_rhs_noalloc.restype = ctypes.c_int
         L.mhd_bench_copy.restype = ctypes.c_int
         L.mhd_load.argtypes = [vp, vp]
@@ -234,6 +239,28 @@ def mhd_rhs_noalloc(p: mhd_params, fields_in, rhs_out, stream_handle: int) -> in
     return int(lib().mhd_rhs_noalloc(ctypes.byref(p), ctypes.c_void_p(fields_in.data_ptr()),
                                      ctypes.c_void_p(rhs_out.data_ptr()), _dtype_code(fields_in),
                                      ctypes.c_void_p(stream_handle)))
+
+
+def _check_tracers(pos, vel):
+    import torch
+
+    for t in (pos, vel):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64 or t.dim() != 2 or t.shape[1] != 3:
+            raise ValueError("tracer arrays must be contiguous float64 CUDA tensors of shape (np, 3)")
+    if pos.shape != vel.shape:
+        raise ValueError("positions and velocities differ in shape")
+
+
+def mhd_tracers_velocity(ctx, pos, vel):
+    _check_tracers(pos, vel)
+    _rc(lib().mhd_tracers_velocity(ctx, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vel.data_ptr()),
+                                   pos.shape[0]), "mhd_tracers_velocity", ctx)
+
+
+def mhd_tracers_push(ctx, pos, vel, dt: float, nsteps: int):
+    _check_tracers(pos, vel)
+    _rc(lib().mhd_tracers_push(ctx, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(vel.data_ptr()),
+                               pos.shape[0], float(dt), int(nsteps)), "mhd_tracers_push", ctx)
 
 
 def mhd_step(ctx, nsteps: int):
@@ -462,6 +489,16 @@ class Solver:
     @property
     def step_bytes(self) -> float:
         return mhd_step_bytes(self.ctx)
+
+    def tracer_velocity(self, pos):
+        """Grid velocity at the tracer positions pos (np, 3) float64 CUDA."""
+        vel = self.torch.empty_like(pos)
+        mhd_tracers_velocity(self.ctx, pos, vel)
+        return vel
+
+    def tracer_push(self, pos, vel, dt, nsteps=1):
+        """Boris-push the tracers in place through nsteps steps of dt."""
+        mhd_tracers_push(self.ctx, pos, vel, dt, nsteps)
 
     @property
     def checkpoint_bytes(self) -> int:
