@@ -85,6 +85,13 @@ int orc_run(const orc_params* p, double* U, int32_t nsteps);
 /* Diagnostics of the state U^ = D F U (see the ORC_* indices). */
 int orc_diag(const orc_params* p, const double* U, double* out);
 
+/* Turbulence diagnostics (Section V) of the state U^ = D F U, with
+ * u = m / rho and u^ = D F u: kinetic and magnetic shell spectra
+ * eu[s], eb[s] (shell s: floor(|k| + 1/2) = s, s < nshell; sum |.|^2 / 2n^6),
+ * and mom = {theta' = <(div u)^2>^(1/2), S_3 = <d^3>/<d^2>^(3/2),
+ * <d^2>^(1/2)} with d = du_x/dx. */
+int orc_spectra(const orc_params* p, const double* U, int32_t nshell, double* eu, double* eb, double* mom);
+
 /* Tracer particles (Section VI).  Positions pos[np][3] = (x, y, z) in
  * [0, 2 pi) (any real value is taken modulo the period).
  * orc_cic: cloud-in-cell interpolation of the real fields f[nc][n^3] at the

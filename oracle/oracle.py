@@ -68,6 +68,8 @@ def lib():
         L.orc_neumaier_sum.restype = ctypes.c_double
         L.orc_num_threads.restype = ctypes.c_int32
         L.orc_set_num_threads.argtypes = [ctypes.c_int32]
+        L.orc_spectra.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_int32, dp, dp, dp]
+        L.orc_spectra.restype = ctypes.c_int
         L.orc_cic.argtypes = [ctypes.c_int32, dp, ctypes.c_int32, dp, ctypes.c_int64, dp]
         L.orc_cic.restype = ctypes.c_int
         L.orc_tracer_push.argtypes = [ctypes.c_int32, dp, dp, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32]
@@ -145,6 +147,15 @@ def diag(U, gamma=5.0 / 3.0, nu=0.0, eta=0.0, cfl=0.1) -> dict:
     p = _params(U.shape[1], gamma, nu, eta, 0.0, cfl)
     _check(lib().orc_diag(ctypes.byref(p), _ptr(U), _ptr(out)), "diag")
     return dict(zip(DIAG_NAMES, out.tolist()))
+
+
+def spectra(U, nshell: int) -> dict:
+    """Shell spectra E_u, E_B (nshell shells) and theta', S_3, <(du_x/dx)^2>^(1/2)."""
+    U = _fields(U)
+    eu, eb, mom = np.zeros(nshell), np.zeros(nshell), np.zeros(3)
+    p = _params(U.shape[1])
+    _check(lib().orc_spectra(ctypes.byref(p), _ptr(U), int(nshell), _ptr(eu), _ptr(eb), _ptr(mom)), "spectra")
+    return {"e_u": eu, "e_b": eb, "theta_rms": mom[0], "s3": mom[1], "dudx_rms": mom[2]}
 
 
 def cic(f, pos) -> np.ndarray:

@@ -558,6 +558,73 @@ int orc_run(const orc_params* p, double* U, int32_t nsteps) {
 }
 
 /* ------------------------------------------------------------------------- */
+/* Turbulence diagnostics of Section V: shell spectra, theta', S_3.           */
+/* ------------------------------------------------------------------------- */
+
+/* Of the state U^ = D F U: u = m / rho on the grid and u^ = D F u (as the
+ * right-hand side forms them).  Shell s holds the modes with
+ * floor(|k| + 1/2) = s;  E_u(s) = sum over the shell of |u^|^2 / (2 n^6) and
+ * E_B(s) likewise of B^ (so sum_s E_B(s) = <|B|^2> / 2 by Parseval).
+ * theta' = <(div u)^2>^(1/2) with div u = F^-1[i k . u^] (Parseval sum);
+ * S_3 = <d^3> / <d^2>^(3/2) with d = du_x/dx = F^-1[i k_x u^_x] on the grid. */
+int orc_spectra(const orc_params* p, const double* Uin, int32_t nshell, double* eu, double* eb, double* mom) {
+    grid g;
+    if (make_grid(p, &g) || !Uin || nshell < 1 || !eu || !eb || !mom) return -1;
+    const int n = g.n;
+    const long n3 = g.n3;
+    cplx** Uh = alloc_spectra(&g, 8);
+    rhs_work w;
+    int err = !Uh ? -2 : alloc_work(&g, &w);
+    if (!err) err = to_state(&g, Uin, Uh);
+    for (int f = 0; f < 8 && !err; ++f) err = inverse(&g, Uh[f], w.c0, w.U[f]);
+    for (int i = 0; i < 3 && !err; ++i) {
+        for (long q = 0; q < n3; ++q) w.u[i][q] = w.U[F_MX + i][q] / w.U[F_RHO][q];
+        err = forward(&g, w.u[i], w.uh[i]);
+        apply_mask(&g, w.uh[i]);
+    }
+    for (int s = 0; s < nshell; ++s) eu[s] = eb[s] = 0.0;
+    double div2 = 0.0;
+    const double inv6 = 1.0 / ((double)n3 * (double)n3);
+    for (int iz = 0; iz < n && !err; ++iz)
+        for (int iy = 0; iy < n; ++iy)
+            for (int ix = 0; ix < n; ++ix) {
+                const double kx = wavenumber(ix, n), ky = wavenumber(iy, n), kz = wavenumber(iz, n);
+                const long id = ((long)iz * n + iy) * n + ix;
+                const int s = (int)floor(sqrt(kx * kx + ky * ky + kz * kz) + 0.5);
+                double a = 0.0, b = 0.0;
+                for (int i = 0; i < 3; ++i) {
+                    a += creal(w.uh[i][id] * conj(w.uh[i][id]));
+                    b += creal(Uh[F_BX + i][id] * conj(Uh[F_BX + i][id]));
+                }
+                if (s < nshell) {
+                    eu[s] += 0.5 * a * inv6;
+                    eb[s] += 0.5 * b * inv6;
+                }
+                const cplx d = I * (kx * w.uh[0][id] + ky * w.uh[1][id] + kz * w.uh[2][id]);
+                div2 += creal(d * conj(d)) * inv6;
+            }
+    if (!err) {
+        times_ik(&g, w.uh[0], 0, 1.0, w.c1);
+        err = inverse(&g, w.c1, w.c0, w.flux);
+    }
+    if (!err) {
+        double* d2 = w.G[0];
+        double* d3 = w.G[1];
+        for (long q = 0; q < n3; ++q) {
+            d2[q] = w.flux[q] * w.flux[q];
+            d3[q] = d2[q] * w.flux[q];
+        }
+        const double m2 = orc_neumaier_sum(d2, n3) / (double)n3, m3 = orc_neumaier_sum(d3, n3) / (double)n3;
+        mom[0] = sqrt(div2);
+        mom[1] = m2 > 0 ? m3 / pow(m2, 1.5) : 0.0;
+        mom[2] = sqrt(m2);
+    }
+    if (Uh) free_work(&w);
+    free_spectra(Uh, 8);
+    return err;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Tracer particles (Section VI): cloud-in-cell interpolation of grid fields  */
 /* to particle positions and the Boris push in the magnetic field.            */
 /* ------------------------------------------------------------------------- */

@@ -89,12 +89,14 @@ def shell_modes(n: int, k_lo: int, k_hi: int):
 
 
 def random_field(n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, rms: float,
-                 slope: float | None = None, solenoidal: bool = True, comp_offset: int = 0) -> np.ndarray:
+                 slope: float | None = None, solenoidal: bool = True, comp_offset: int = 0,
+                 spectrum=None) -> np.ndarray:
     """Gaussian random field (ncomp, n, n, n) in shells [k_lo, k_hi].
 
     slope=alpha shapes the shell energy spectrum to E(k) ~ k^alpha (coefficient
-    amplitude ~ |k|^((alpha-2)/2)); None leaves it white.  rms is the target
-    <|f|^2>^(1/2) over all components."""
+    amplitude ~ |k|^((alpha-2)/2)); spectrum=E (a function of |k|) shapes it to
+    E(|k|) (amplitude ~ (E(|k|) / |k|^2)^(1/2)); neither leaves it white.  rms
+    is the target <|f|^2>^(1/2) over all components."""
     kz, ky, kx = shell_modes(n, k_lo, k_hi)
     nh = n // 2 + 1
     coef = np.zeros((ncomp, kz.size), dtype=np.complex128)
@@ -105,6 +107,8 @@ def random_field(n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, rms: float
     kk = np.sqrt((kx * kx + ky * ky + kz * kz).astype(np.float64))
     if slope is not None:
         coef *= kk ** ((slope - 2.0) / 2.0)
+    if spectrum is not None:
+        coef *= np.sqrt(spectrum(kk) / (kk * kk))
     if solenoidal:
         assert ncomp == 3
         kv = np.stack([kx, ky, kz]).astype(np.float64)  # component order x, y, z
@@ -288,6 +292,21 @@ def trig_state(seed: int, rho_amp: float = 0.15, u_amp: float = 0.4, b_amp: floa
         mask = [j != i for j in range(3)]  # (x, y, z): B_i independent of x_i
         t[f"B{i}"] = (float(rng.uniform(-0.3, 0.3)), terms(b_amp / 3, mask))
     return TrigState(t)
+
+
+def decaying_turbulence(n: int = 64, k0: float = 4.0, mach: float = 0.1, nu: float = 2e-3,
+                        seed: int = 8, gamma: float = 5.0 / 3.0, name: str = "decay") -> Case:
+    """The hydrodynamic decaying-turbulence start of Section V-A: rho = 1,
+    solenoidal u with E(k) = A k^4 exp(-2 k^2 / k0^2) over every retained
+    shell, rms 1 (<|u|^2>^(1/2) = U0 = 1), uniform P from the Mach number
+    (c_s = U0 / M), B = 0, nu = eta; dt from the CFL condition."""
+    K = (n - 1) // 3
+    u = random_field(n, seed, 3, 1, K, 1.0, spectrum=lambda k: k ** 4 * np.exp(-2.0 * k * k / (k0 * k0)))
+    rho = np.ones((n, n, n))
+    cs = 1.0 / mach
+    P = np.full((n, n, n), cs * cs / gamma)
+    U = conserved(rho, u, np.zeros((3, n, n, n)), P, gamma)
+    return Case(name, U, gamma, nu, nu, cfl_dt(U, gamma), 1000, {"mach": mach, "k0": k0})
 
 
 # The workloads of the paper's 3D MHD runs as concrete synthetic inputs.
