@@ -76,8 +76,13 @@ enum {
     MHD_FLAG_VISC_LAPLACIAN = 4, /* viscous force nu lap u (Section V's momentum equation) instead of
                                     div(2 nu rho S) (Eq. MHD2); the energy gains nu lap(|u|^2/2), its work
                                     plus heating, so <E> stays conserved */
-    MHD_FLAG_KINEMATIC = 8       /* kinematic dynamo (Section V-B): rho, m and E are frozen and only the
+    MHD_FLAG_KINEMATIC = 8,      /* kinematic dynamo (Section V-B): rho, m and E are frozen and only the
                                     induction equation evolves, under the frozen flow */
+    MHD_FLAG_SCHEDULE_ALT = 16   /* run the alternative kernel schedule (radix plans with one radix-16
+                                    stage, 8-column tiles), built for MHD_FP32 at n = 32, 64, 96, 128 only
+                                    (MHD_E_SIZE elsewhere); the ensemble autotuner chooses between the two
+                                    schedules per group, and a single run with this flag reproduces a
+                                    member run on that schedule bit for bit */
 };
 
 /* Time integrators (mhd_params.scheme); Section II names all three and finds
@@ -188,6 +193,16 @@ int mhd_rhs(mhd_ctx* ctx, const void* d_fields_in, void* d_rhs_out, int32_t dtyp
 int mhd_rhs_noalloc(const mhd_params* p, const void* d_fields_in, void* d_rhs_out, int32_t dtype,
                     void* hip_stream);
 
+/* Switches the kernel schedule of the context's later right-hand sides and
+ * steps (0 = default build, 1 = the MHD_FLAG_SCHEDULE_ALT build); the state,
+ * the history and the transforms of set/get/diagnostics are unaffected (both
+ * builds lay out the compact spectra identically).  A run whose state was set
+ * on the default build and then switched reproduces an ensemble member on
+ * that schedule bit for bit (members get their states before the tuner
+ * runs).  MHD_E_SIZE where the build does not exist (the context keeps its
+ * schedule); MHD_E_ARG for other values. */
+int mhd_set_schedule(mhd_ctx* ctx, int32_t schedule);
+
 /* Advances the state by nsteps >= 0 steps of the Adams-Bashforth scheme
  * (Sections II and IV; second order, fixed dt):
  * U^{n+1} = U^n + dt (3/2 R^n - 1/2 R^{n-1}); the first step after
@@ -207,6 +222,22 @@ int mhd_step(mhd_ctx* ctx, int32_t nsteps);
  * steps' largest signal speed is kept and reduced in FP64); *h_out is filled
  * either way.  MHD_E_STATE if no state is set. */
 int mhd_diagnostics(mhd_ctx* ctx, mhd_diag* h_out);
+
+/* Turbulence diagnostics of Section V (its decaying-turbulence and MHD
+ * runs): shell spectra and velocity-gradient statistics of the current state,
+ * in FP64 from the compact spectra, with u = m/rho formed on the grid and
+ * u^ = D F[u] as the right-hand side forms them.  Shell s holds the retained
+ * modes with floor(|k| + 1/2) = s, s = 0 .. mhd_spectra_shells(n) - 1.
+ *   h_eu[s] = sum over shell s of |u^|^2 / (2 n^6)  (kinetic spectrum per unit mass)
+ *   h_eb[s] = sum over shell s of |B^|^2 / (2 n^6)  (sums to <|B|^2>/2)
+ *   h_mom[0] = theta' = <(div u)^2>^(1/2)  (Parseval)
+ *   h_mom[1] = S_3 = <d^3> / <d^2>^(3/2), d = du_x/dx on the grid
+ *   h_mom[2] = <d^2>^(1/2)
+ * Host arrays of mhd_spectra_shells(n) (h_eu, h_eb) and 3 (h_mom) doubles.
+ * Synchronises the stream; uses the workspace's scratch (not the state).
+ * MHD_E_STATE if no state is set. */
+int32_t mhd_spectra_shells(int32_t n);
+int mhd_spectra(mhd_ctx* ctx, double* h_eu, double* h_eb, double* h_mom);
 
 /* Tracer particles (Section VI): passive particles sprinkled in the box,
  * moved by the magnetic field of the grid.  d_pos, d_vel: caller-owned FP64
@@ -365,11 +396,12 @@ int mhd_ens_diagnostics(mhd_ens* ens, mhd_diag* h_out, int32_t* h_status);
 /* Number of member groups (equal n and precision, at most 64 members). */
 int32_t mhd_ens_num_groups(const mhd_ens* ens);
 
-/* Group g's grid size, precision, member count and tuned persistent-grid
- * scales (column passes, row passes; 1 = resident-occupancy grid).  Any
+/* Group g's grid size, precision, member count, tuned persistent-grid
+ * scales (column passes, row passes; 1 = resident-occupancy grid) and tuned
+ * kernel schedule (0 = default, 1 = the MHD_FLAG_SCHEDULE_ALT build).  Any
  * output pointer may be NULL. */
 int mhd_ens_group_info(const mhd_ens* ens, int32_t g, int32_t* n, int32_t* precision, int32_t* members,
-                       double* col_scale, double* row_scale);
+                       double* col_scale, double* row_scale, int32_t* schedule);
 
 /* Algorithmic HBM bytes of one mhd_ens_step over all members. */
 double mhd_ens_step_bytes(const mhd_ens* ens);

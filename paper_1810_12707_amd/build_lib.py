@@ -19,6 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libmhd.so")
 SIZES = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
+SCHED1_SIZES = (32, 64, 96, 128)  # sizes with an alternative-schedule build (the ensemble's)
 ARCH = "gfx950"
 
 
@@ -59,6 +60,10 @@ def build(jobs: int | None = None, sizes=SIZES, verbose: bool = True) -> str:
             tasks.append((os.path.join(CSRC, "mhd_inst.hip"), os.path.join(BUILD, f"mhd_inst_{n}.o"), [f"-DMHD_N={n}"]))
         else:
             tasks.append((os.path.join(CSRC, "mhd_stub.hip"), os.path.join(BUILD, f"mhd_stub_{n}.o"), [f"-DMHD_N={n}"]))
+    for n in SCHED1_SIZES:
+        src = "mhd_inst.hip" if n in sz else "mhd_stub.hip"
+        tasks.append((os.path.join(CSRC, src), os.path.join(BUILD, f"{src[:-4]}_s1_{n}.o"),
+                      [f"-DMHD_N={n}", "-DMHD_SCHED=1"]))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = [ex.submit(_compile, *t) for t in tasks]
         objs = [f.result() for f in futs]

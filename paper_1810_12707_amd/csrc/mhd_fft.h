@@ -23,7 +23,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include "mhd_internal.h"
+
 namespace mhd {
+MHD_SCHED_BEGIN
 
 template <typename T> struct V2;
 template <> struct V2<float> { using t = float2; };
@@ -193,15 +196,24 @@ template <int NN, bool MXX, int... Rs> struct PlanT {
 template <int N, bool MX> struct PlanSel;
 #define MHD_PLAN(NN, ...) template <> struct PlanSel<NN, false> { using type = PlanT<NN, false, __VA_ARGS__>; };
 #define MHD_PLAN_MX(NN, ...) template <> struct PlanSel<NN, true> { using type = PlanT<NN, true, __VA_ARGS__>; };
+// The alternative schedule (ensemble sizes only) takes one radix-16 stage:
+// fewer LDS passes, more registers per butterfly.
 MHD_PLAN(8, 8)
 MHD_PLAN(12, 4, 3)
 MHD_PLAN(16, 4, 4)
 MHD_PLAN(24, 8, 3)
-MHD_PLAN(32, 8, 4)
 MHD_PLAN(48, 4, 4, 3)
+#if MHD_SCHED == 1
+MHD_PLAN(32, 2, 16)
+MHD_PLAN(64, 4, 16)
+MHD_PLAN(96, 2, 3, 16)
+MHD_PLAN(128, 8, 16)
+#else
+MHD_PLAN(32, 8, 4)
 MHD_PLAN(64, 8, 8)
 MHD_PLAN(96, 8, 4, 3)
 MHD_PLAN(128, 8, 4, 4)
+#endif
 MHD_PLAN(192, 8, 8, 3)
 MHD_PLAN(256, 8, 8, 4)
 MHD_PLAN(384, 8, 4, 4, 3)
@@ -540,16 +552,18 @@ __device__ __forceinline__ void fft_pass_valu(cx<T>* buf, const cx<T>* tw, int t
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// A-operand halves of the 16-point DFT as a real 32 x 32 matrix for this lane
-// (row q = lane mod 16; k-range 8 (lane / 16) .. +8 of the (Re x, Im x) inputs):
-// block 0 gives Re y_q, block 1 Im y_q.
+// A-operand halves of the 16-point DFT as a real 32 x 32 matrix for this lane.
+// The 32 real inputs are ordered with Re and Im interleaved, k = 2 r + c
+// (c = 0: Re x_r, c = 1: Im x_r); lane (q = lane mod 16, g = lane / 16) holds
+// row q, k = 8 g .. 8 g + 7, i.e. inputs r = 4 g .. 4 g + 3.  Block 0 gives
+// Re y_q, block 1 Im y_q.
 template <int S>
 __device__ __forceinline__ void dft16_operands(int lane, bf16x8& a0h, bf16x8& a0l, bf16x8& a1h, bf16x8& a1l) {
   const int q = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
-    const int r = (8 * g + t) & 15;  // input index
-    const bool im_in = g >= 2;       // column block of Im x
+    const int r = 4 * g + (t >> 1);  // input index
+    const bool im_in = (t & 1) != 0;  // Im x_r
     const int m = (q * r) & 15;
     const float re = float(kCos16[m]);
     const float im = float(S) * float(kCos16[(m + 12) & 15]);
@@ -565,9 +579,10 @@ __device__ __forceinline__ void dft16_operands(int lane, bf16x8& a0h, bf16x8& a0
 
 // Radix-16 Stockham pass on the MFMA units (FP32 data, split BF16 x 3).  Each
 // wave takes 16 butterflies at a time: lane (n = lane mod 16, g = lane / 16)
-// reads elements 8 (g mod 2) .. +8 of butterfly n, twiddles them in FP32 and
-// keeps their real (g < 2) or imaginary (g >= 2) parts as the B operand; after
-// the products lane (n, g) holds outputs q = 4g .. 4g+3 of butterfly n.
+// reads elements 4 g .. 4 g + 3 of butterfly n, twiddles them in FP32 and
+// splits their real and imaginary parts into the B operand (k = 2 r + c, as
+// in dft16_operands); after the products lane (n, g) holds outputs
+// q = 4g .. 4g+3 of butterfly n.
 template <class PL, int NB, int NT, int ES, int BS, int S, int P, int MAP, int PADSH>
 __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int tid, int b_act) {
   static_assert(!wave_map<MAP>(), "MFMA passes use the workgroup lane maps");
@@ -594,8 +609,8 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
     const int k = j % NS;
     bf16x8 xh, xl;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = 8 * (g & 1) + t;
+    for (int e = 0; e < 4; ++e) {
+      const int r = 4 * g + e;
       float2 x = ok ? buf[lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)] : make_float2(0.f, 0.f);
       if constexpr (NS > 1) {
         if (r > 0) {
@@ -603,10 +618,11 @@ __device__ __forceinline__ void fft_pass_mfma(float2* buf, const float2* tw, int
           x = (S < 0) ? cmul(x, tv) : cmulc(x, tv);
         }
       }
-      const float val = g < 2 ? x.x : x.y;
-      const __bf16 h = (__bf16)val;
-      xh[t] = h;
-      xl[t] = (__bf16)(val - (float)h);
+      const __bf16 hr = (__bf16)x.x, hi = (__bf16)x.y;
+      xh[2 * e] = hr;
+      xl[2 * e] = (__bf16)(x.x - (float)hr);
+      xh[2 * e + 1] = hi;
+      xl[2 * e + 1] = (__bf16)(x.y - (float)hi);
     }
     floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
     c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, xh, c0, 0, 0, 0);
@@ -680,17 +696,18 @@ __device__ __forceinline__ void fft_pass_mfma_last(const float2* buf, const floa
     }
     bf16x8 xh, xl;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int r = 8 * (g & 1) + t;
+    for (int e = 0; e < 4; ++e) {
+      const int r = 4 * g + e;
       float2 x = ok ? buf[lds_at<ES, BS, PADSH, PL, P>(b, j + r * NBF)] : make_float2(0.f, 0.f);
       if (r > 0) {
         const float2 tv = tw[j * r];  // k = j in the last pass
         x = (S < 0) ? cmul(x, tv) : cmulc(x, tv);
       }
-      const float val = g < 2 ? x.x : x.y;
-      const __bf16 h = (__bf16)val;
-      xh[t] = h;
-      xl[t] = (__bf16)(val - (float)h);
+      const __bf16 hr = (__bf16)x.x, hi = (__bf16)x.y;
+      xh[2 * e] = hr;
+      xl[2 * e] = (__bf16)(x.x - (float)hr);
+      xh[2 * e + 1] = hi;
+      xl[2 * e + 1] = (__bf16)(x.y - (float)hi);
     }
     floatx4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
     c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, xh, c0, 0, 0, 0);
@@ -999,4 +1016,5 @@ __device__ __forceinline__ int xcd_remap(int w, int total) {
   return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
+MHD_SCHED_END
 }  // namespace mhd

@@ -8,6 +8,7 @@
 //      --> forward z with divergence / curl, resistive term and the AB2 update.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,6 +30,9 @@ Registry& registry() {
 #define MHD_CALL_REGISTER(NN) register_##NN(*reg);
     MHD_SIZES(MHD_CALL_REGISTER)
 #undef MHD_CALL_REGISTER
+#define MHD_CALL_REGISTER_S1(NN) register_s1_##NN(*reg);
+    MHD_SCHED1_SIZES(MHD_CALL_REGISTER_S1)
+#undef MHD_CALL_REGISTER_S1
     return reg;
   }();
   return *r;
@@ -355,6 +359,70 @@ __global__ void __launch_bounds__(kThreads) k_tracer_push(const T* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------------ spectra
+// Turbulence diagnostics of Section V over the compact spectra.  Shell s holds
+// the modes with floor(|k| + 1/2) = s.  Block b takes entries b, b + G, ...
+// (padding skipped); a kx > 0 entry stands for itself and its conjugate (x2).
+// Per block: raw shell sums sum |u^|^2 and sum |B^|^2 and sum |k.u^|^2 in LDS
+// (FP64 LDS atomics: the order of additions inside a block is not fixed, so
+// a block's sums are reproducible to FP64 rounding), written to
+// part[b][2 nsh + 1] and reduced over blocks by k_reduce.
+constexpr int kSpecBlocks = 256;
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_spectra(const T* __restrict__ uh, const T* __restrict__ bh, Geo g,
+                                                     int nsh, double* __restrict__ part) {
+  extern __shared__ double bins[];  // 2 nsh + 1
+  const int nb = 2 * nsh + 1;
+  for (int i = threadIdx.x; i < nb; i += kThreads) bins[i] = 0.0;
+  __syncthreads();
+  const int64_t plane = (int64_t)g.nb * g.nhp;
+  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < g.sc;
+       idx += (int64_t)gridDim.x * kThreads) {
+    const int lz = (int)(idx / plane);
+    const int rem = (int)(idx - (int64_t)lz * plane);
+    const int ly = rem / g.nhp, kx = rem - ly * g.nhp;
+    if (kx >= g.nh) continue;
+    const int kz = lz <= g.K ? lz : lz - g.nb;
+    const int ky = ly <= g.K ? ly : ly - g.nb;
+    const double w = kx == 0 ? 1.0 : 2.0;
+    const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+    const int s = (int)floor(sqrt(k2) + 0.5);
+    double a = 0.0, b = 0.0, dr = 0.0, di = 0.0;
+    const double kv[3] = {double(kx), double(ky), double(kz)};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double ur = uh[2 * (i * g.sc + idx)], ui = uh[2 * (i * g.sc + idx) + 1];
+      const double br = bh[2 * (i * g.sc + idx)], bi = bh[2 * (i * g.sc + idx) + 1];
+      a += ur * ur + ui * ui;
+      b += br * br + bi * bi;
+      dr += kv[i] * ur;
+      di += kv[i] * ui;
+    }
+    if (s < nsh) {
+      atomicAdd(&bins[s], w * a);
+      atomicAdd(&bins[nsh + s], w * b);
+    }
+    atomicAdd(&bins[2 * nsh], w * (dr * dr + di * di));
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += kThreads) part[(int64_t)blockIdx.x * nb + i] = bins[i];
+}
+
+// Per-thread Neumaier sums of d^2 and d^3 over a real field d[n3] (grid-stride);
+// thread t of block b writes its compensated pair sums to part[(b T + t)][2].
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_moments(const T* __restrict__ d, int64_t n3, double* __restrict__ part) {
+  double s2 = 0.0, c2 = 0.0, s3 = 0.0, c3 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kThreads) {
+    const double v = double(d[i]);
+    two_sum_into(s2, c2, v * v);
+    two_sum_into(s3, c3, v * v * v);
+  }
+  const int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  part[2 * r] = s2 + c2;
+  part[2 * r + 1] = s3 + c3;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_spec_diag(const T* __restrict__ bx, const T* __restrict__ by, const T* __restrict__ bz, Geo g,
@@ -506,8 +574,11 @@ Geo make_geo(int n) {
   return g;
 }
 
+// Shells of the retained modes: floor(|k| + 1/2) <= floor(sqrt(3) K + 1/2).
+int spectrum_shells(int K) { return (int)std::floor(std::sqrt(3.0) * K + 0.5) + 1; }
+
 struct Layout {
-  size_t tw, state, rprev, uhat, tstate, trhs, force, iz, iy, part, spart, status, res, hash, total;
+  size_t tw, state, rprev, uhat, tstate, trhs, force, iz, iy, part, spart, status, res, hash, shpart, shres, total;
 };
 
 Layout make_layout(const Geo& g, size_t tsize) {
@@ -531,6 +602,9 @@ Layout make_layout(const Geo& g, size_t tsize) {
   L.status = take((size_t)kStatusSlots * 2 * sizeof(double));
   L.res = take(kResWords * sizeof(double));
   L.hash = take(sizeof(uint64_t));
+  const size_t nbins = 2 * (size_t)spectrum_shells(g.K) + 1;
+  L.shpart = take(std::max(nbins * kSpecBlocks, (size_t)2 * kSpecBlocks * kThreads) * sizeof(double));
+  L.shres = take((nbins + 2) * sizeof(double));
   L.total = off;
   return L;
 }
@@ -1039,6 +1113,10 @@ bool is_fp32(int32_t prec) { return prec == MHD_FP32 || prec == MHD_MIXED; }
 
 const void* kern_for(const mhd_ctx* c) {
   Registry& r = registry();
+  if (c->p.flags & MHD_FLAG_SCHEDULE_ALT) {
+    if (c->p.precision != MHD_FP32) return nullptr;
+    return r.f32s1[c->p.n].row ? &r.f32s1[c->p.n] : nullptr;
+  }
   if (c->p.precision == MHD_FP32) return r.f32[c->p.n].row ? &r.f32[c->p.n] : nullptr;
   if (c->p.precision == MHD_MIXED) return r.mx[c->p.n].row ? &r.mx[c->p.n] : nullptr;
   return r.f64[c->p.n].row ? &r.f64[c->p.n] : nullptr;
@@ -1083,6 +1161,8 @@ int validate_member(const mhd_params* p) {
 
 }  // namespace
 
+static int ctx_geometry(mhd_ctx* c);
+
 // Sets up a context in place (no allocation): parameters, layout, launch
 // geometry and the twiddle table, uploaded through a host buffer on the stack
 // (synchronously).  The workspace must have been checked by the caller.
@@ -1098,6 +1178,30 @@ static int ctx_setup(mhd_ctx* c, const mhd_params* p, void* d_workspace, size_t 
   c->first_step = true;
   c->step = 0;
   c->t = 0.0;
+  const int rg = ctx_geometry(c);
+  if (rg != MHD_OK) return rg;
+  // twiddles exp(-2 pi i j / n) in FP64, rounded once to the working precision
+  const int n = p->n;
+  const double two_pi = 6.28318530717958647692528676655900577;
+  double h64[2 * 1024];
+  float h32[2 * 1024];
+  for (int j = 0; j < n; ++j) {
+    const double cr = std::cos(two_pi * j / n), ci = -std::sin(two_pi * j / n);
+    h64[2 * j] = cr;
+    h64[2 * j + 1] = ci;
+    h32[2 * j] = (float)cr;
+    h32[2 * j + 1] = (float)ci;
+  }
+  const void* src = is_fp32(p->precision) ? static_cast<const void*>(h32) : static_cast<const void*>(h64);
+  hipError_t e = hipMemcpyAsync(c->ws + c->L.tw, src, 2 * (size_t)n * ts, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host buffer dies with this frame
+  return e == hipSuccess ? MHD_OK : MHD_E_HIP;
+}
+
+// Launch geometry of the context's kernels (their resident workgroups per CU
+// times the CU count); redone when an ensemble group switches schedule.
+static int ctx_geometry(mhd_ctx* c) {
+  const mhd_params* p = &c->p;
   const void* kv = kern_for(c);
   if (!kv) return MHD_E_SIZE;
   int dev = 0;
@@ -1117,22 +1221,7 @@ static int ctx_setup(mhd_ctx* c, const mhd_params* p, void* d_workspace, size_t 
                        f32 ? static_cast<const Kern<float>*>(kv)->col_occupancy(1, 3)
                            : static_cast<const Kern<double>*>(kv)->col_occupancy(1, 3)};
   for (int m = 0; m < 3; ++m) c->col_blocks[m] = cocc[m] * c->num_cus;
-  // twiddles exp(-2 pi i j / n) in FP64, rounded once to the working precision
-  const int n = p->n;
-  const double two_pi = 6.28318530717958647692528676655900577;
-  double h64[2 * 1024];
-  float h32[2 * 1024];
-  for (int j = 0; j < n; ++j) {
-    const double cr = std::cos(two_pi * j / n), ci = -std::sin(two_pi * j / n);
-    h64[2 * j] = cr;
-    h64[2 * j + 1] = ci;
-    h32[2 * j] = (float)cr;
-    h32[2 * j + 1] = (float)ci;
-  }
-  const void* src = f32 ? static_cast<const void*>(h32) : static_cast<const void*>(h64);
-  e = hipMemcpyAsync(c->ws + c->L.tw, src, 2 * (size_t)n * ts, hipMemcpyHostToDevice, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);  // the host buffer dies with this frame
-  return e == hipSuccess ? MHD_OK : MHD_E_HIP;
+  return MHD_OK;
 }
 
 static int ctx_check(const mhd_params* p, void* d_workspace, size_t ws_bytes) {
@@ -1322,6 +1411,7 @@ struct EnsGroup {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   double col_scale = 1.0, row_scale = 1.0;  // persistent-grid scales (tuned)
+  int sched = 0;                            // kernel schedule (tuned): 0 default, 1 MHD_FLAG_SCHEDULE_ALT
   bool tuned = false;
 };
 
@@ -1389,24 +1479,36 @@ int ens_launch(mhd_ens* E, hipStream_t origin, bool rhs_only) {
   return e == hipSuccess ? MHD_OK : ens_fail(E, e, "ensemble launch");
 }
 
+// Switches group G's launches to kernel schedule `sched` (the lead context
+// takes that build's kernels and launch geometry; the members' own contexts,
+// used for set/get/diagnostics, keep the default build: both lay out the
+// compact spectra identically).  MHD_E_SIZE if the build does not exist.
+int set_schedule(EnsGroup& G, int sched) {
+  const int rc = mhd_set_schedule(G.lead, sched);
+  if (rc == MHD_OK) G.sched = sched;
+  return rc;
+}
+
 std::string tune_key(const EnsGroup& G, int cus) {
   char b[96];
   std::snprintf(b, sizeof(b), "%d %d %d %d", G.n, G.precision, (int)G.members.size(), cus);
   return b;
 }
 
-// Cache lines: "mhd-ens-tune <n> <precision> <members> <CUs> <col_scale> <row_scale>".
+// Cache lines: "mhd-ens-tune <n> <precision> <members> <CUs> <col_scale> <row_scale> <schedule>".
 void tune_read(mhd_ens* E) {
   FILE* f = std::fopen(E->tune_path.c_str(), "r");
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof(line), f)) {
-    int n, pr, nm, cus;
+    int n, pr, nm, cus, sc = 0;
     double cs, rs;
-    if (std::sscanf(line, "mhd-ens-tune %d %d %d %d %lf %lf", &n, &pr, &nm, &cus, &cs, &rs) != 6) continue;
-    if (!(cs > 0.0 && cs <= 4.0 && rs > 0.0 && rs <= 4.0)) continue;
+    const int got = std::sscanf(line, "mhd-ens-tune %d %d %d %d %lf %lf %d", &n, &pr, &nm, &cus, &cs, &rs, &sc);
+    if (got < 6) continue;
+    if (!(cs > 0.0 && cs <= 4.0 && rs > 0.0 && rs <= 4.0) || sc < 0 || sc > 1) continue;
     for (EnsGroup& G : E->groups) {
       if (G.n == n && G.precision == pr && (int)G.members.size() == nm && E->num_cus == cus) {
+        if (sc == 1 && set_schedule(G, 1) != MHD_OK) continue;  // no such build: keep tuning
         G.col_scale = cs;
         G.row_scale = rs;
         G.tuned = true;
@@ -1419,7 +1521,8 @@ void tune_read(mhd_ens* E) {
 void tune_write(mhd_ens* E, const EnsGroup& G) {
   FILE* f = std::fopen(E->tune_path.c_str(), "a");
   if (!f) return;  // an unwritable cache only costs a re-tune next time
-  std::fprintf(f, "mhd-ens-tune %s %.4f %.4f\n", tune_key(G, E->num_cus).c_str(), G.col_scale, G.row_scale);
+  std::fprintf(f, "mhd-ens-tune %s %.4f %.4f %d\n", tune_key(G, E->num_cus).c_str(), G.col_scale, G.row_scale,
+               G.sched);
   std::fclose(f);
 }
 
@@ -1441,28 +1544,45 @@ int ens_time(mhd_ens* E, int reps, double* ms) {
 }
 
 // One sweep of coordinate search over the groups: for each untuned group,
-// the persistent-grid scales of its column and row passes that give the
-// fastest whole-ensemble evaluation, the other groups held at their current
-// scales.
+// the kernel schedule (the default build, or the alternative one where it
+// exists) and the persistent-grid scales of its column and row passes that
+// give the fastest whole-ensemble evaluation, the other groups held at their
+// current choices.  A choice other than the default (default build, full
+// grids) must beat the default by kTuneMargin, so that timing noise between
+// near-equal choices does not change the pick from run to run.
+constexpr double kTuneMargin = 0.03;
 int ens_tune(mhd_ens* E) {
   static const double kScales[] = {0.25, 0.5, 1.0};
   for (EnsGroup& G : E->groups) {
     if (G.tuned) continue;
-    double best = 1e300, bc = 1.0, br = 1.0;
-    for (double cs : kScales) {
-      for (double rs : kScales) {
-        G.col_scale = cs;
-        G.row_scale = rs;
-        double t = 0.0;
-        int rc = ens_time(E, 3, &t);
-        if (rc != MHD_OK) return rc;
-        if (t < best) {
-          best = t;
-          bc = cs;
-          br = rs;
+    double best = 1e300, bc = 1.0, br = 1.0, t_default = 1e300;
+    int bs = 0;
+    for (int sched = 0; sched < 2; ++sched) {
+      if (set_schedule(G, sched) != MHD_OK) continue;  // no alternative build for this (n, precision)
+      for (double cs : kScales) {
+        for (double rs : kScales) {
+          G.col_scale = cs;
+          G.row_scale = rs;
+          double t = 0.0;
+          int rc = ens_time(E, 3, &t);
+          if (rc != MHD_OK) return rc;
+          if (sched == 0 && cs == 1.0 && rs == 1.0) t_default = t;
+          if (t < best) {
+            best = t;
+            bc = cs;
+            br = rs;
+            bs = sched;
+          }
         }
       }
     }
+    if (!(best < (1.0 - kTuneMargin) * t_default)) {
+      bs = 0;
+      bc = 1.0;
+      br = 1.0;
+    }
+    const int rc = set_schedule(G, bs);
+    if (rc != MHD_OK) return rc;
     G.col_scale = bc;
     G.row_scale = br;
     G.tuned = true;
@@ -1619,6 +1739,24 @@ int mhd_rhs_noalloc(const mhd_params* p, const void* d_in, void* d_out, int32_t 
   return mhd_rhs(&c, d_in, d_out, dtype);  // every launch is enqueued (arguments copied) when this returns
 }
 
+int mhd_set_schedule(mhd_ctx* c, int32_t schedule) {
+  if (!c || schedule < 0 || schedule > 1) return MHD_E_ARG;
+  const int32_t old = c->p.flags;
+  c->p.flags = schedule ? (old | MHD_FLAG_SCHEDULE_ALT) : (old & ~MHD_FLAG_SCHEDULE_ALT);
+  const int rc = ctx_geometry(c);
+  if (rc != MHD_OK) {
+    c->p.flags = old;
+    (void)ctx_geometry(c);
+    return rc;
+  }
+  // the captured step belongs to the other build
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->exec = nullptr;
+  c->graph = nullptr;
+  return MHD_OK;
+}
+
 int mhd_step(mhd_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return MHD_E_ARG;
   if (!c->has_state) return MHD_E_STATE;
@@ -1717,6 +1855,62 @@ int mhd_load(mhd_ctx* c, const void* d_blob) {
 }
 
 int mhd_diagnostics(mhd_ctx* c, mhd_diag* h) { return ctx_diag(c, h); }
+
+int32_t mhd_spectra_shells(int32_t n) {
+  if (n < 1) return 0;
+  return spectrum_shells((n - 1) / 3);
+}
+
+int mhd_spectra(mhd_ctx* c, double* h_eu, double* h_eb, double* h_mom) {
+  if (!c || !h_eu || !h_eb || !h_mom) return MHD_E_ARG;
+  if (!c->has_state) return MHD_E_STATE;
+  const Geo& g = c->g;
+  const int nsh = spectrum_shells(g.K);
+  const int nb = 2 * nsh + 1;
+  double* shpart = reinterpret_cast<double*>(c->ws + c->L.shpart);
+  double* shres = reinterpret_cast<double*>(c->ws + c->L.shres);
+  int rc = with_engine(c, [&](auto& e) {
+    using T = std::remove_pointer_t<decltype(e.state())>;
+    e.phase_a(e.state());  // u^ = D F[m / rho] of the current state
+    hipLaunchKernelGGL((k_spectra<T>), dim3(kSpecBlocks), dim3(kThreads), nb * sizeof(double), c->stream,
+                       e.uhat(), e.spec_field(e.state(), 4), g, nsh, shpart);
+    hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(kThreads), 0, c->stream, shpart, (int64_t)kSpecBlocks, nb, 0u,
+                       shpart, (int64_t)0, 0, shres, shres);
+    // d = du_x/dx = F^-1[i k_x u^_x] on the grid, then its second and third moments
+    const T* zi[1] = {e.uhat()};
+    T* zo[1] = {e.iz(0)};
+    OutSpec sp[1] = {spec({term(0, 0, e.inv_n3())})};
+    e.col(PK_ZINV, 1, zi, 1, zo, sp);
+    T* yo[1] = {e.iy(0)};
+    e.y_copy(PK_YINV, 1, zo, yo);
+    RowArgs<T> r = e.row_args();
+    T* real = e.iy(4);
+    r.real_out = real;
+    r.real_dtype = sizeof(T) == 4 ? 1 : 0;
+    r.nf = 1;
+    e.set_in(r, 0);
+    e.k.row(RM_XINV_REAL, r, e.row_grid(RM_XINV_REAL), c->stream);
+    hipLaunchKernelGGL((k_moments<T>), dim3(kSpecBlocks), dim3(kThreads), 0, c->stream, real, g.n3, shpart);
+    hipLaunchKernelGGL(k_reduce, dim3(2), dim3(kThreads), 0, c->stream, shpart, (int64_t)kSpecBlocks * kThreads, 2,
+                       0u, shpart, (int64_t)0, 0, shres + nb, shres + nb);
+    return check_launch(c, "mhd_spectra");
+  });
+  if (rc != MHD_OK) return rc;
+  std::vector<double> res(nb + 2);
+  hipError_t err = hipMemcpyAsync(res.data(), shres, (nb + 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(c->stream);
+  if (err != hipSuccess) return hip_fail(c, err, "mhd_spectra copy");
+  const double n3 = (double)g.n3, inv6 = 1.0 / (n3 * n3);
+  for (int s = 0; s < nsh; ++s) {
+    h_eu[s] = 0.5 * res[s] * inv6;
+    h_eb[s] = 0.5 * res[nsh + s] * inv6;
+  }
+  const double m2 = res[nb] / n3, m3 = res[nb + 1] / n3;
+  h_mom[0] = std::sqrt(res[2 * nsh] * inv6);
+  h_mom[1] = m2 > 0 ? m3 / std::pow(m2, 1.5) : 0.0;
+  h_mom[2] = std::sqrt(m2);
+  return MHD_OK;
+}
 
 // Tracers: the real-space fields they need are synthesised from the state
 // into the I_y scratch from slot 4 on (at most four fields: 4 n^3 words, at
@@ -2001,7 +2195,7 @@ int mhd_ens_diagnostics(mhd_ens* E, mhd_diag* h_out, int32_t* h_status) {
 int32_t mhd_ens_num_groups(const mhd_ens* E) { return E ? (int32_t)E->groups.size() : 0; }
 
 int mhd_ens_group_info(const mhd_ens* E, int32_t g, int32_t* n, int32_t* precision, int32_t* members,
-                       double* col_scale, double* row_scale) {
+                       double* col_scale, double* row_scale, int32_t* schedule) {
   if (!E || g < 0 || g >= (int32_t)E->groups.size()) return MHD_E_ARG;
   const EnsGroup& G = E->groups[g];
   if (n) *n = G.n;
@@ -2009,6 +2203,7 @@ int mhd_ens_group_info(const mhd_ens* E, int32_t g, int32_t* n, int32_t* precisi
   if (members) *members = (int32_t)G.members.size();
   if (col_scale) *col_scale = G.col_scale;
   if (row_scale) *row_scale = G.row_scale;
+  if (schedule) *schedule = G.sched;
   return MHD_OK;
 }
 

@@ -92,6 +92,10 @@ Kern<T> make() {
 
 #define MHD_CAT2(a, b) a##b
 #define MHD_CAT(a, b) MHD_CAT2(a, b)
+#if MHD_SCHED == 1
+// the alternative schedule: FP32 only
+void MHD_CAT(register_s1_, MHD_N)(Registry& r) { r.f32s1[MHD_N] = make<float, MHD_N, false>(); }
+#else
 void MHD_CAT(register_, MHD_N)(Registry& r) {
   r.f32[MHD_N] = make<float, MHD_N, false>();
   r.mx[MHD_N] = make<float, MHD_N, true>();
@@ -99,5 +103,6 @@ void MHD_CAT(register_, MHD_N)(Registry& r) {
   r.f64[MHD_N] = make<double, MHD_N, false>();
 #endif
 }
+#endif
 
 }  // namespace mhd

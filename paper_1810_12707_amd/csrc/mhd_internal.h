@@ -16,6 +16,21 @@
 #include <cstdint>
 #include <type_traits>
 
+// Kernel schedules.  The pass kernels (mhd_fft.h, mhd_kernels.h) are compiled
+// once per grid size with the default schedule and, for the ensemble sizes,
+// once more with the alternative schedule (MHD_SCHED = 1: other radix plans
+// and narrower column tiles).  Each build lives in its own inline namespace,
+// so the two sets of template instances never collide at link time.
+#ifndef MHD_SCHED
+#define MHD_SCHED 0
+#endif
+#if MHD_SCHED == 1
+#define MHD_SCHED_BEGIN inline namespace sched1 {
+#else
+#define MHD_SCHED_BEGIN inline namespace sched0 {
+#endif
+#define MHD_SCHED_END }
+
 namespace mhd {
 
 constexpr int kThreads = 256;  // threads per workgroup of every pass kernel

@@ -15,6 +15,7 @@
 #include "mhd_internal.h"
 
 namespace mhd {
+MHD_SCHED_BEGIN
 
 template <int N> struct Band {
   static constexpr int K = (N - 1) / 3;
@@ -28,9 +29,11 @@ template <int N> __device__ __forceinline__ int band_pos(int l) { return l <= Ba
 template <int N> __device__ __forceinline__ int band_k(int l) { return l <= Band<N>::K ? l : l - Band<N>::NB; }
 
 // Default column tile: 16 columns while the LDS tile stays within 32 KiB,
-// else 8.
+// else 8.  The alternative schedule takes 8-column tiles (twice the work
+// items, half the LDS per workgroup).
 template <typename T, int N> constexpr int col_width() {
   constexpr int bytes = N * 2 * (int)sizeof(T);
+  if (MHD_SCHED == 1) return 8;
   return 32768 / bytes >= 16 ? 16 : 8;
 }
 
@@ -682,10 +685,11 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     }
   };
   // per-workgroup accumulators of the diagnostic / status modes: the largest
-  // signal speed (each point's speed is formed in T; the max is held in FP64)
-  // and the non-finite count of the flux pass; Neumaier (sum, compensation)
-  // pairs of the diagnostics pass
-  double cfl = 0.0;
+  // signal speed (each point's speed is formed in T, and the thread's maximum
+  // of T values is exact in T; it goes to FP64 at the workgroup's flush) and
+  // the non-finite count of the flux pass; Neumaier (sum, compensation) pairs
+  // of the diagnostics pass
+  T cfl = T(0);
   int bad = 0;
   double q[kDiagQ], qc[kDiagQ];
 #pragma unroll
@@ -705,8 +709,8 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
     if constexpr (MODE == RM_XB) {
       if (mem != cur_m) {  // uniform across the workgroup
         if (cur_m >= 0 && a.status) {
-          flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
-          cfl = 0.0;
+          flush_status<NT>(double(cfl), bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
+          cfl = T(0);
           bad = 0;
         }
         cur_m = mem;
@@ -891,7 +895,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
           // fastest signal speed for the CFL limit, and a non-finite check
           const T umax = fmax(fabs(ux), fmax(fabs(uy), fabs(uz)));
           const T c = umax + sqrt_((gam * P + B2) * ir);
-          if (!(double(c) <= cfl)) cfl = double(c);  // NaN propagates
+          if (!(c <= cfl)) cfl = c;  // NaN propagates
           const bool fin = finite_(rho) && finite_(mx) && finite_(my) && finite_(mz) && finite_(Bx) &&
                            finite_(By) && finite_(Bz) && finite_(E);
           bad += fin ? 0 : 1;
@@ -973,7 +977,7 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   }
 
   if constexpr (MODE == RM_XB) {
-    if (cur_m >= 0 && a.status) flush_status<NT>(cfl, bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
+    if (cur_m >= 0 && a.status) flush_status<NT>(double(cfl), bad, member_ptr(a.status, cur_m, a.bt.mstride), red);
   }
   if constexpr (MODE == RM_XDIAG) {
     for (int i = 0; i < kDiagQ; ++i) {
@@ -984,4 +988,5 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
   }
 }
 
+MHD_SCHED_END
 }  // namespace mhd

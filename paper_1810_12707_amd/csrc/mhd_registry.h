@@ -24,7 +24,8 @@ struct Kern {
 struct Registry {
   Kern<float> f32[1025];
   Kern<double> f64[1025];
-  Kern<float> mx[1025];  // FP32 data, radix-16 stages on MFMA (split BF16 x 3)
+  Kern<float> mx[1025];    // FP32 data, radix-16 stages on MFMA (split BF16 x 3)
+  Kern<float> f32s1[1025];  // FP32, alternative schedule (ensemble sizes)
 };
 
 Registry& registry();
@@ -33,5 +34,11 @@ Registry& registry();
 #define MHD_DECLARE_REGISTER(NN) void register_##NN(Registry&);
 MHD_SIZES(MHD_DECLARE_REGISTER)
 #undef MHD_DECLARE_REGISTER
+
+// Sizes with an alternative-schedule build (the batched ensemble's sizes).
+#define MHD_SCHED1_SIZES(X) X(32) X(64) X(96) X(128)
+#define MHD_DECLARE_REGISTER_S1(NN) void register_s1_##NN(Registry&);
+MHD_SCHED1_SIZES(MHD_DECLARE_REGISTER_S1)
+#undef MHD_DECLARE_REGISTER_S1
 
 }  // namespace mhd

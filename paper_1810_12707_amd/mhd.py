@@ -24,6 +24,7 @@ MHD_FLAG_CHECK_CFL = 1
 MHD_FLAG_NO_GRAPH = 2
 MHD_FLAG_VISC_LAPLACIAN = 4
 MHD_FLAG_KINEMATIC = 8
+MHD_FLAG_SCHEDULE_ALT = 16
 MHD_AB2, MHD_RK4, MHD_PC = 0, 1, 2
 SCHEMES = {"ab2": MHD_AB2, "rk4": MHD_RK4, "pc": MHD_PC}
 
@@ -32,7 +33,7 @@ EXPORTED = (
     "mhd_rhs", "mhd_step", "mhd_diagnostics", "mhd_fft3d", "mhd_spectrum_size", "mhd_spectrum_pitch", "mhd_destroy",
     "mhd_status_string", "mhd_last_error", "mhd_profile", "mhd_profile_read", "mhd_step_bytes",
     "mhd_checkpoint_bytes", "mhd_save", "mhd_load", "mhd_bench_copy", "mhd_rhs_noalloc",
-    "mhd_tracers_velocity", "mhd_tracers_push",
+    "mhd_tracers_velocity", "mhd_tracers_push", "mhd_spectra_shells", "mhd_spectra", "mhd_set_schedule",
     "mhd_ens_workspace_bytes", "mhd_ens_init", "mhd_ens_set_state", "mhd_ens_get_state", "mhd_ens_step",
     "mhd_ens_diagnostics", "mhd_ens_num_groups", "mhd_ens_group_info", "mhd_ens_step_bytes", "mhd_ens_destroy",
     "mhd_ens_last_error",
@@ -119,6 +120,12 @@ def lib() -> ctypes.CDLL:
         L.mhd_save.argtypes = [vp, vp]
         L.mhd_bench_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
         L.mhd_rhs_noalloc.argtypes = [P, vp, vp, ctypes.c_int32, vp]
+        L.mhd_set_schedule.argtypes = [vp, ctypes.c_int32]
+        L.mhd_set_schedule.restype = ctypes.c_int
+        L.mhd_spectra_shells.argtypes = [ctypes.c_int32]
+        L.mhd_spectra_shells.restype = ctypes.c_int32
+        L.mhd_spectra.argtypes = [vp, dp, dp, dp]
+        L.mhd_spectra.restype = ctypes.c_int
         L.mhd_tracers_velocity.argtypes = [vp, vp, vp, ctypes.c_int64]
         L.mhd_tracers_velocity.restype = ctypes.c_int
         L.mhd_tracers_push.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int32]
@@ -137,7 +144,7 @@ def lib() -> ctypes.CDLL:
         L.mhd_ens_num_groups.argtypes = [vp]
         L.mhd_ens_num_groups.restype = i32
         ip = ctypes.POINTER(i32)
-        L.mhd_ens_group_info.argtypes = [vp, i32, ip, ip, ip, dp, dp]
+        L.mhd_ens_group_info.argtypes = [vp, i32, ip, ip, ip, dp, dp, ip]
         L.mhd_ens_step_bytes.argtypes = [vp]
         L.mhd_ens_step_bytes.restype = ctypes.c_double
         L.mhd_ens_destroy.argtypes = [vp]
@@ -239,6 +246,21 @@ def mhd_rhs_noalloc(p: mhd_params, fields_in, rhs_out, stream_handle: int) -> in
     return int(lib().mhd_rhs_noalloc(ctypes.byref(p), ctypes.c_void_p(fields_in.data_ptr()),
                                      ctypes.c_void_p(rhs_out.data_ptr()), _dtype_code(fields_in),
                                      ctypes.c_void_p(stream_handle)))
+
+
+def mhd_set_schedule(ctx, schedule: int):
+    _rc(lib().mhd_set_schedule(ctx, int(schedule)), "mhd_set_schedule", ctx)
+
+
+def mhd_spectra_shells(n: int) -> int:
+    return int(lib().mhd_spectra_shells(int(n)))
+
+
+def mhd_spectra(ctx, n: int) -> dict:
+    ns = mhd_spectra_shells(n)
+    eu, eb, mom = (ctypes.c_double * ns)(), (ctypes.c_double * ns)(), (ctypes.c_double * 3)()
+    _rc(lib().mhd_spectra(ctx, eu, eb, mom), "mhd_spectra", ctx)
+    return {"e_u": list(eu), "e_b": list(eb), "theta_rms": mom[0], "s3": mom[1], "dudx_rms": mom[2]}
 
 
 def _check_tracers(pos, vel):
@@ -392,11 +414,12 @@ def mhd_ens_num_groups(ens) -> int:
 
 
 def mhd_ens_group_info(ens, g: int) -> dict:
-    n, pr, nm = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    n, pr, nm, sc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     cs, rs = ctypes.c_double(), ctypes.c_double()
     _rc_ens(lib().mhd_ens_group_info(ens, int(g), ctypes.byref(n), ctypes.byref(pr), ctypes.byref(nm),
-                                     ctypes.byref(cs), ctypes.byref(rs)), "mhd_ens_group_info", ens)
-    return {"n": n.value, "precision": pr.value, "members": nm.value, "col_scale": cs.value, "row_scale": rs.value}
+                                     ctypes.byref(cs), ctypes.byref(rs), ctypes.byref(sc)), "mhd_ens_group_info", ens)
+    return {"n": n.value, "precision": pr.value, "members": nm.value, "col_scale": cs.value, "row_scale": rs.value,
+            "schedule": sc.value}
 
 
 def mhd_ens_step_bytes(ens) -> float:
@@ -489,6 +512,14 @@ class Solver:
     @property
     def step_bytes(self) -> float:
         return mhd_step_bytes(self.ctx)
+
+    def set_schedule(self, schedule: int):
+        """Kernel schedule of later steps (0 default, 1 the alternative build)."""
+        mhd_set_schedule(self.ctx, schedule)
+
+    def spectra(self) -> dict:
+        """Section V turbulence diagnostics of the current state (see mhd_spectra)."""
+        return mhd_spectra(self.ctx, self.n)
 
     def tracer_velocity(self, pos):
         """Grid velocity at the tracer positions pos (np, 3) float64 CUDA."""

@@ -89,6 +89,16 @@ def test_ensemble_members_take_the_plain_ab2_configuration(M):
         assert M.mhd_ens_workspace_bytes([ok, bad]) == 0
 
 
+def test_alternative_schedule_exists_only_for_fp32_ensemble_sizes(M):
+    L = M.lib()
+    ctx = ctypes.c_void_p()
+    for n, prec in ((48, M.MHD_FP32), (256, M.MHD_FP32), (32, M.MHD_FP64), (64, M.MHD_MIXED)):
+        p = M.make_params(n, prec, flags=M.MHD_FLAG_SCHEDULE_ALT)
+        need = M.mhd_workspace_bytes(p)
+        # refused before any device work (the workspace pointer is never touched)
+        assert L.mhd_init(ctypes.byref(p), ctypes.c_void_p(4096), need, None, ctypes.byref(ctx)) == M.MHD_E_SIZE
+
+
 def test_bad_size_and_workspace(M):
     L = M.lib()
     ctx = ctypes.c_void_p()

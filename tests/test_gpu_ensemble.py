@@ -41,10 +41,27 @@ def make_ensemble(spec, cases, tune_cache=None):
     return Ensemble([member_dict(n, p, c) for (n, p, _), c in zip(spec, cases)], tune_cache=tune_cache)
 
 
-def make_solo(n, prec, c):
-    from paper_1810_12707_amd.mhd import Solver
+def make_solo(n, prec, c, schedule=0):
+    from paper_1810_12707_amd.mhd import MHD_FLAG_SCHEDULE_ALT, Solver
 
-    return Solver(n, precision=prec, gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt)
+    return Solver(n, precision=prec, gamma=c.gamma, nu=c.nu, eta=c.eta, dt=c.dt,
+                  flags=MHD_FLAG_SCHEDULE_ALT if schedule else 0)
+
+
+def solo_like_member(n, prec, c, schedule):
+    """A solo run that reproduces an ensemble member: its state is set on the
+    default build (as the members' are, before the tuner runs), then its
+    steps switch to the schedule the member's group was tuned to."""
+    S = make_solo(n, prec, c)
+    S.set_state(dev(c.U))
+    S.set_schedule(schedule)
+    return S
+
+
+def schedule_of(E, n, prec):
+    """The kernel schedule the tuner chose for the (n, precision) group."""
+    code = {"fp64": 0, "fp32": 1, "mixed": 2}[prec]
+    return [g["schedule"] for g in E.groups() if g["n"] == n and g["precision"] == code][0]
 
 
 def states_equal(a, b):
@@ -59,17 +76,19 @@ def test_members_match_solo_runs_bitwise():
     log("  groups", groups)
     assert sorted((g["n"], g["precision"], g["members"]) for g in groups) == [(16, 1, 3), (16, 2, 1), (24, 0, 1),
                                                                               (24, 1, 1), (32, 1, 1)]
-    solos = []
-    for i, ((n, p, _), c) in enumerate(zip(MEMBERS, cases)):
+    for i, c in enumerate(cases):
         E.set_state(i, dev(c.U))
-        S = make_solo(n, p, c)
-        S.set_state(dev(c.U))
-        solos.append(S)
-    E.step(1)   # Euler start, eager
+    E.step(1)   # tuning (schedules, grids), Euler start, eager
     E.step(5)   # AB2 steps, graph replays
-    for S in solos:
+    solos = []
+    for (n, p, _), c in zip(MEMBERS, cases):
+        S = solo_like_member(n, p, c, schedule_of(E, n, p))  # on the schedule its group was tuned to
         S.step(1)
         S.step(5)
+        # read back on the default build, as the member's own context does (the
+        # builds' inverse transforms round differently; the steps are the test)
+        S.set_schedule(0)
+        solos.append(S)
     rc, st, diags = E.diagnostics()
     log("  status", st)
     assert rc == 0 and st == [0] * len(MEMBERS)
@@ -90,7 +109,7 @@ def test_reset_and_poisoned_member():
     log("[ens] reset one member, poison another")
     spec = [(16, "fp32", 10), (16, "fp32", 11), (24, "fp32", 12), (16, "fp32", 13)]
     cases = [case(n, s) for n, _, s in spec]
-    E = make_ensemble(spec, cases)
+    E = make_ensemble(spec, cases, tune_cache="")  # untuned: the default schedule and grids
     solos = [make_solo(n, p, c) for (n, p, _), c in zip(spec, cases)]
     for i, c in enumerate(cases):
         E.set_state(i, dev(c.U))
@@ -177,3 +196,76 @@ def test_tune_cache_roundtrip(tmp_path):
     E2.step(2)
     assert len(path.read_text().strip().splitlines()) == 2  # nothing re-tuned
     E2.close()
+
+
+def test_ensemble_sizes_bitwise_on_their_tuned_schedules():
+    """The benchmark ensemble's sizes (32, 64, 96, 128; FP32): the tuner picks
+    a schedule and grid per group; every member equals a solo run on that
+    schedule bit for bit, and each schedule is held to the oracle."""
+    log("[ens] sizes 32/64/96/128, tuned")
+    spec = [(32, "fp32", 40), (64, "fp32", 41), (96, "fp32", 42), (128, "fp32", 43), (32, "fp32", 44),
+            (64, "fp32", 45)]
+    cases = [case(n, s) for n, _, s in spec]
+    E = make_ensemble(spec, cases)
+    for i, c in enumerate(cases):
+        E.set_state(i, dev(c.U))
+    E.step(1)
+    E.step(4)
+    log("  groups", E.groups())
+    for i, ((n, p, _), c) in enumerate(zip(spec, cases)):
+        sched = schedule_of(E, n, p)
+        S = solo_like_member(n, p, c, sched)
+        S.step(5)
+        S.set_schedule(0)  # read back on the default build, as the member's context does
+        assert states_equal(E.get_state(i), S.get_state()), f"member {i} (n={n}, schedule {sched})"
+        S.close()
+    E.close()
+
+
+@pytest.mark.parametrize("n", [32, 64, 96, 128])
+def test_alternative_schedule_matches_oracle(n):
+    """The alternative kernel build (radix plans with one radix-16 stage,
+    8-column tiles) is held to the oracle like the default one: 10 AB2 steps,
+    FP32 bound 1e-5 per field."""
+    log(f"[ens] alternative schedule n={n}")
+    c = case(n, 50 + n)
+    S = make_solo(n, "fp32", c, schedule=1)
+    S.set_state(dev(c.U))
+    S.step(10)
+    got = S.get_state().cpu().numpy()
+    S.close()
+    ref = O.run(c.U, 10, c.dt, c.gamma, c.nu, c.eta)
+    errs = per_field_rel_l2(got, ref)
+    log("  ", ["%.2e" % e for e in errs])
+    assert max(errs) <= 1e-5
+
+
+def test_schedule_switch_where_no_alternative_exists():
+    """mhd_set_schedule refuses a build that does not exist (MHD_E_SIZE) and
+    leaves the context on its schedule; switching back and forth between the
+    builds leaves a run valid (its next steps on the chosen build)."""
+    from paper_1810_12707_amd.mhd import MHD_E_SIZE, MHDError
+
+    c = case(48, 60)
+    S = make_solo(48, "fp32", c)
+    S.set_state(dev(c.U))
+    with pytest.raises(MHDError) as e:
+        S.set_schedule(1)
+    assert e.value.status == MHD_E_SIZE
+    S.step(2)
+    ref = O.run(c.U, 2, c.dt, c.gamma, c.nu, c.eta)
+    assert max(per_field_rel_l2(S.get_state().cpu().numpy(), ref)) <= 1e-5
+    S.close()
+    c = case(64, 61)
+    S = make_solo(64, "fp32", c)
+    S.set_state(dev(c.U))
+    S.step(2)
+    S.set_schedule(1)
+    S.step(2)
+    S.set_schedule(0)
+    S.step(2)
+    ref = O.run(c.U, 6, c.dt, c.gamma, c.nu, c.eta)
+    errs = per_field_rel_l2(S.get_state().cpu().numpy(), ref)
+    log(f"[ens] schedule switches at n=64: {max(errs):.2e}")
+    assert max(errs) <= 1e-5
+    S.close()
