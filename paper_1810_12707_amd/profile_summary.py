@@ -94,16 +94,18 @@ def per_kernel_kib(path: str, counter: str) -> dict:
     return {k: (v[0] / v[1], v[1]) for k, v in acc.items()}
 
 
-# Launch classes of one FP32 step in launch order, with the kernel each uses.
+# Launch classes of one step in launch order, with the kernel each uses
+# ({mx}: false on the FP32 path, true on the mixed path).
 STEP_SEQUENCE = [
-    ("zinv_a", "k_col<float, {n}, 1,"), ("yinv_a", "k_col<float, {n}, 1,"), ("xa", "k_row<float, {n}, 0, false>"),
-    ("yfwd_a", "k_col<float, {n}, -1,"), ("zfwd_a", "k_col<float, {n}, -1,"), ("zinv_b", "k_col<float, {n}, 1, 3,"),
-    ("yinv_b", "k_col<float, {n}, 1,"), ("xb", "k_row<float, {n}, 1, false>"), ("yfwd_b", "k_col<float, {n}, -1,"),
-    ("rho", "k_rho_rhs<float>"), ("zrhs", "k_zfwd_rhs<float, {n}, false>"),
+    ("zinv_a", "k_col<float, {n}, 1, 1, {mx}>"), ("yinv_a", "k_col<float, {n}, 1, 1, {mx}>"),
+    ("xa", "k_row<float, {n}, 0, {mx}>"), ("yfwd_a", "k_col<float, {n}, -1, 1, {mx}>"),
+    ("zfwd_a", "k_col<float, {n}, -1, 1, {mx}>"), ("zinv_b", "k_col<float, {n}, 1, 3, {mx}>"),
+    ("yinv_b", "k_col<float, {n}, 1, 1, {mx}>"), ("xb", "k_row<float, {n}, 1, {mx}>"),
+    ("yfwd_b", "k_col<float, {n}, -1, 1, {mx}>"), ("rho", "k_rho_rhs<float>"), ("zrhs", "k_zfwd_rhs<float, {n}, {mx}>"),
 ]
 
 
-def per_class_kib(path: str, counter: str, n: int) -> dict:
+def per_class_kib(path: str, counter: str, n: int, mixed: bool = False) -> dict:
     """Mean counter value (KiB) per launch class: dispatches are matched to the
     step's fixed launch sequence (steps interrupted by other launches, such as
     diagnostics, are skipped)."""
@@ -113,7 +115,8 @@ def per_class_kib(path: str, counter: str, n: int) -> dict:
             if r["Counter_Name"] == counter:
                 recs.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
     recs.sort()
-    seq = [(c, k.format(n=n)) for c, k in STEP_SEQUENCE]
+    mx = "true" if mixed else "false"
+    seq = [(c, k.format(n=n, mx=mx)) for c, k in STEP_SEQUENCE]
     acc = defaultdict(lambda: [0.0, 0])
     i = 0
     while i + len(seq) <= len(recs):
@@ -202,7 +205,7 @@ def cmd_pmc(a) -> int:
                 names.add(r["Counter_Name"])
         for c in sorted(names):
             counters.append(c)
-            table[c] = per_class_kib(path, c, a.n)
+            table[c] = per_class_kib(path, c, a.n, a.mixed)
     lines = [f"# Hardware counters per launch: {a.title}", "", "Commands (<repo> = the repository root; one pass "
              "per counter group):", "", "```", a.command, "```", "",
              "Mean value per launch of each class (dispatches matched to the step's launch sequence).", "",
@@ -250,6 +253,7 @@ def main(argv=None) -> int:
     c.add_argument("--title", default="")
     c.add_argument("--out", required=True)
     c.add_argument("--note", default="")
+    c.add_argument("--mixed", action="store_true", help="the mixed path's launches (else FP32's)")
     a = ap.parse_args(argv)
     return {"stats": cmd_stats, "traffic": cmd_traffic, "pmc": cmd_pmc}[a.what](a)
 
