@@ -388,9 +388,10 @@ template <class PL, int STG> __device__ __forceinline__ int stage_swz(int row) {
     if constexpr (NSW >= 16 || !is_pow2(NSW) || !is_pow2(RW) || PL::N % 16 != 0) {
       return 0;
     } else if constexpr (NSW * RW >= 16) {
-      return ((row / (NSW * RW / 16)) % (16 / NSW)) << ilog2(NSW);
+      // row >= 0: unsigned arithmetic, so the powers of two become shifts and masks
+      return (int)((((unsigned)row / (NSW * RW / 16)) % (16 / NSW)) << ilog2(NSW));
     } else {
-      return (row % RW) << ilog2(NSW);
+      return (int)(((unsigned)row % RW) << ilog2(NSW));
     }
   }
 }

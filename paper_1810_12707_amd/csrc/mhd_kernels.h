@@ -961,14 +961,41 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
         st(dst, row0 * NHP + k, x0);
         st(dst, (row0 + 1) * NHP + k, x1);
       };
+      // the same with the field's output row as one wave-uniform pointer
+      auto unpack_row = [&](cx<T>* dst, int fld, int k) {
+        const cx<T> zk = buf[at(fld, k)];
+        const cx<T> zm = buf[at(fld, k == 0 ? 0 : N - k)];
+        dst[k] = mk<T>(zk.x + zm.x, zk.y - zm.y);
+        dst[NHP + k] = mk<T>(zk.y + zm.y, zm.x - zk.x);
+      };
       if constexpr (WAVE) {
         // each wave unpacks the fields it transformed
         constexpr int W = NT / 64;
         const int wv = tid >> 6;
-        for (int e = tid & 63; e < seqs_per_wave<NB, NT>() * NH; e += 64) {
-          const int fl = e / NH;
-          const int fld = fl * W + wv;
-          if (fld < nout) unpack(fld, e - fl * NH);
+        // The flux pass at N <= 256 (at most two 64-wide sweeps of a field)
+        // unpacks field by field with the sweeps unrolled: the field, its
+        // output row and the LDS addresses are then wave-uniform or stay in
+        // registers across row pairs.  Elsewhere that costs occupancy, and
+        // the flattened (field, k) walk is kept.
+        constexpr int KIT = (NH + 63) / 64;
+        if constexpr (MODE == RM_XB && KIT <= 2) {
+          cx<T>* const row_out = reinterpret_cast<cx<T>*>(out0) + row0 * NHP;
+          for (int fl = 0; fl < seqs_per_wave<NB, NT>(); ++fl) {
+            const int fld = fl * W + wv;
+            if (fld >= nout) break;
+            cx<T>* const dst = row_out + fld * ost;
+#pragma unroll
+            for (int it = 0; it < KIT; ++it) {
+              const int k = (tid & 63) + 64 * it;
+              if ((it + 1) * 64 <= NH || k < NH) unpack_row(dst, fld, k);
+            }
+          }
+        } else {
+          for (int e = tid & 63; e < seqs_per_wave<NB, NT>() * NH; e += 64) {
+            const int fl = e / NH;
+            const int fld = fl * W + wv;
+            if (fld < nout) unpack(fld, e - fl * NH);
+          }
         }
       } else {
         for (int e = tid; e < nout * NH; e += NT) unpack(e / NH, e - (e / NH) * NH);
