@@ -264,6 +264,15 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
         v[i][r] = acc;
       }
     }
+    // The next item's loads go out before this item's first pass where that
+    // measured faster (FP32 forward and three-term passes from N = 256: 3-6%
+    // at 512), else after it; either way they are in flight during the LDS
+    // passes.
+    constexpr bool EARLY = sizeof(T) == 4 && !MX && N >= 256 && (S < 0 || MAXT > 1);
+    const int next = (int)xcd_item(blockIdx.x, G, k + 1, total);
+    if constexpr (EARLY) {
+      if (next >= 0) issue(decode(next));
+    }
     __syncthreads();  // the previous item's last pass is done reading the tile
     T* out = member_ptr(a.out[it.f], it.m, a.bt.mstride);
     const int64_t base_out = it.outer * os_out + it.c0;
@@ -277,8 +286,9 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
       st(out, base_out + l * ls_out + c, val);
     };
     fft_first_regs<T, PL, C, NT, C, 1, S, 0, 0>(tile, v, tid, C, store);
-    const int next = (int)xcd_item(blockIdx.x, G, k + 1, total);
-    if (next >= 0) issue(decode(next));  // in flight during this item's LDS passes
+    if constexpr (!EARLY) {
+      if (next >= 0) issue(decode(next));
+    }
     // mixed plans: one-term passes overlap two MFMA groups (the three-term
     // inverse pass would spill)
     fft_rest<T, PL, C, NT, C, 1, S, 0, 0, false, false, (MAXT == 1 ? 2 : 1)>(tile, stw, tid, C, store);

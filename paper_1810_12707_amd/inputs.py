@@ -88,15 +88,11 @@ def shell_modes(n: int, k_lo: int, k_hi: int):
     return kz[keep], ky[keep], kx[keep]
 
 
-def random_field(n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, rms: float,
-                 slope: float | None = None, solenoidal: bool = True, comp_offset: int = 0,
-                 spectrum=None) -> np.ndarray:
-    """Gaussian random field (ncomp, n, n, n) in shells [k_lo, k_hi].
-
-    slope=alpha shapes the shell energy spectrum to E(k) ~ k^alpha (coefficient
-    amplitude ~ |k|^((alpha-2)/2)); spectrum=E (a function of |k|) shapes it to
-    E(|k|) (amplitude ~ (E(|k|) / |k|^2)^(1/2)); neither leaves it white.  rms
-    is the target <|f|^2>^(1/2) over all components."""
+def shell_coefficients(n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, slope: float | None = None,
+                       solenoidal: bool = True, comp_offset: int = 0, spectrum=None):
+    """The seeded Fourier coefficients of random_field (before its rms
+    scaling): the modes (kz, ky, kx), kx >= 0, of shells [k_lo, k_hi] and an
+    (ncomp, modes) complex array."""
     kz, ky, kx = shell_modes(n, k_lo, k_hi)
     nh = n // 2 + 1
     coef = np.zeros((ncomp, kz.size), dtype=np.complex128)
@@ -114,6 +110,20 @@ def random_field(n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, rms: float
         kv = np.stack([kx, ky, kz]).astype(np.float64)  # component order x, y, z
         kdot = (kv * coef).sum(axis=0) / (kk * kk)
         coef = coef - kv * kdot
+    return (kz, ky, kx), coef
+
+
+def random_field(n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, rms: float,
+                 slope: float | None = None, solenoidal: bool = True, comp_offset: int = 0,
+                 spectrum=None) -> np.ndarray:
+    """Gaussian random field (ncomp, n, n, n) in shells [k_lo, k_hi].
+
+    slope=alpha shapes the shell energy spectrum to E(k) ~ k^alpha (coefficient
+    amplitude ~ |k|^((alpha-2)/2)); spectrum=E (a function of |k|) shapes it to
+    E(|k|) (amplitude ~ (E(|k|) / |k|^2)^(1/2)); neither leaves it white.  rms
+    is the target <|f|^2>^(1/2) over all components."""
+    (kz, ky, kx), coef = shell_coefficients(n, seed, ncomp, k_lo, k_hi, slope, solenoidal, comp_offset, spectrum)
+    nh = n // 2 + 1
     out = np.empty((ncomp, n, n, n), dtype=np.float64)
     for c in range(ncomp):
         spec = np.zeros((n, n, nh), dtype=np.complex128)
@@ -122,6 +132,50 @@ def random_field(n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, rms: float
     cur = math.sqrt(float(np.mean(np.sum(out * out, axis=0))))
     if cur > 0:
         out *= rms / cur
+    return out
+
+
+def mode_planes(torch, n: int, modes, coef: np.ndarray, z0: int, z1: int, device=None):
+    """Planes z0 <= z < z1 of the field random_field synthesises from `coef`
+    (before its rms scaling), as an explicit sum over the few modes instead of
+    a full-size inverse FFT: (ncomp, z1 - z0, n, n) FP64 torch tensor.  The
+    inverse real FFT of a half spectrum holding coef_k at k = (kz, ky, kx),
+    kx >= 0, is sum_k w_k Re(coef_k exp(i k.x)) / n^3 with w = 1 on the kx = 0
+    plane (there the real transform keeps only the real part) and 2 elsewhere."""
+    kz, ky, kx = modes
+    f64 = torch.float64
+    h = 2.0 * math.pi / n
+    z = (torch.arange(z0, z1, dtype=f64, device=device) * h)[:, None, None]
+    y = (torch.arange(n, dtype=f64, device=device) * h)[None, :, None]
+    x = (torch.arange(n, dtype=f64, device=device) * h)[None, None, :]
+    ncomp = coef.shape[0]
+    out = torch.zeros((ncomp, z1 - z0, n, n), dtype=f64, device=device)
+    n3 = float(n) ** 3
+    for m in range(kz.size):
+        th = (float(kz[m]) * z + float(ky[m]) * y) + float(kx[m]) * x
+        c, s = torch.cos(th), torch.sin(th)
+        w = (1.0 if kx[m] == 0 else 2.0) / n3
+        for comp in range(ncomp):
+            a = complex(coef[comp, m])
+            out[comp].add_(c, alpha=w * a.real).add_(s, alpha=-w * a.imag)
+    return out
+
+
+def random_field_device(torch, n: int, seed: int, ncomp: int, k_lo: int, k_hi: int, rms: float, device=None,
+                        chunk: int = 64, **kw):
+    """random_field (up to rounding) built on `device`, plane chunk by plane
+    chunk: (ncomp, n, n, n) FP64 tensor."""
+    modes, coef = shell_coefficients(n, seed, ncomp, k_lo, k_hi, **kw)
+    out = torch.empty((ncomp, n, n, n), dtype=torch.float64, device=device)
+    ss = 0.0
+    for z0 in range(0, n, chunk):
+        z1 = min(n, z0 + chunk)
+        p = mode_planes(torch, n, modes, coef, z0, z1, device)
+        out[:, z0:z1] = p
+        ss += float(torch.sum(p * p))
+    cur = math.sqrt(ss / float(n) ** 3)
+    if cur > 0:
+        out.mul_(rms / cur)
     return out
 
 
@@ -226,6 +280,40 @@ def orszag_tang(n: int = 1024, nu: float = 5e-4, eta: float = 5e-4, steps: int =
     P = np.full((n, n, n), 5.0 / 3.0)
     U = conserved(rho, u, B, P, gamma)
     return Case(name, U, gamma, nu, eta, cfl_dt(U, gamma), steps, {})
+
+
+def orszag_tang_device(torch, n: int = 1024, device=None, dtype=None, nu: float = 5e-4, eta: float = 5e-4,
+                       steps: int = 50, seed: int = 4, amp: float = 1e-2, gamma: float = 5.0 / 3.0,
+                       name: str = "ot", chunk: int = 64) -> Case:
+    """orszag_tang (up to rounding) built on `device` (no n^3 host array):
+    Case whose U is an (8, n, n, n) torch tensor of `dtype` (FP32 unless
+    given) on that device."""
+    f64 = torch.float64
+    dtype = dtype or torch.float32
+    h = 2.0 * math.pi / n
+    u = random_field_device(torch, n, seed, 3, 1, 4, amp, device, chunk)
+    B = random_field_device(torch, n, seed, 3, 1, 4, amp, device, chunk, comp_offset=3)
+    x = torch.arange(n, dtype=f64, device=device) * h
+    u[0] -= torch.sin(x)[None, :, None]
+    u[1] += torch.sin(x)[None, None, :]
+    B[0] -= torch.sin(x)[None, :, None]
+    B[1] += torch.sin(2.0 * x)[None, None, :]
+    rho, P = 25.0 / 9.0, 5.0 / 3.0
+    U = torch.empty((8, n, n, n), dtype=dtype, device=device)
+    smax = 0.0
+    for z0 in range(0, n, chunk):
+        z1 = min(n, z0 + chunk)
+        uc, Bc = u[:, z0:z1], B[:, z0:z1]
+        u2, B2 = torch.sum(uc * uc, dim=0), torch.sum(Bc * Bc, dim=0)
+        U[0, z0:z1] = rho
+        U[1:4, z0:z1] = (rho * uc).to(dtype)
+        U[4:7, z0:z1] = Bc.to(dtype)
+        U[7, z0:z1] = (P / (gamma - 1.0) + 0.5 * rho * u2 + 0.5 * B2).to(dtype)
+        cf = torch.sqrt((gamma * P + B2) / rho)
+        smax = max(smax, float(torch.max(torch.amax(torch.abs(uc), dim=0) + cf)))
+    del u, B
+    dt = 0.1 * h / smax
+    return Case(name, U, gamma, nu, eta, dt, steps, {})
 
 
 def compressive_state(n: int, seed: int, gamma: float = 5.0 / 3.0) -> np.ndarray:

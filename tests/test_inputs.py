@@ -105,3 +105,23 @@ def test_turbulence_recipe():
     P0 = (1.0 / 0.3) ** 2 / c.gamma  # isentropic, sound speed 1 / mach at rho = 1
     assert np.allclose(P, P0 * rho ** c.gamma, rtol=1e-12)
     assert c.dt > 0 and np.isfinite(c.dt)
+
+
+@pytest.mark.parametrize("n", [16, 24])
+def test_device_builders_equal_the_host_recipes(n):
+    """The mode-by-mode device builders (used where an n^3 host array and a
+    full-size inverse FFT would take minutes, 1024^3) synthesise the same
+    fields as the host recipes: random_field with and without the solenoidal
+    projection, and the Orszag-Tang start with its CFL step (run here on the
+    CPU through torch)."""
+    torch = pytest.importorskip("torch")
+    a = I.random_field(n, 7, 3, 1, 4, 0.3, comp_offset=3)
+    b = I.random_field_device(torch, n, 7, 3, 1, 4, 0.3, chunk=5, comp_offset=3).numpy()
+    assert np.abs(a - b).max() <= 1e-13
+    a = I.random_field(n, 9, 1, 1, 4, 1.0, solenoidal=False)
+    b = I.random_field_device(torch, n, 9, 1, 1, 4, 1.0, chunk=n, solenoidal=False).numpy()
+    assert np.abs(a - b).max() <= 1e-13
+    c = I.orszag_tang(n, name="ot")
+    d = I.orszag_tang_device(torch, n, dtype=torch.float64, chunk=7)
+    assert np.abs(c.U - d.U.numpy()).max() <= 1e-13 * np.abs(c.U).max()
+    assert abs(c.dt - d.dt) <= 1e-14 * c.dt
