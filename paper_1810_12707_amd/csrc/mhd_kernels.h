@@ -979,32 +979,30 @@ __global__ void __launch_bounds__((row_threads<T, N, MODE, MX>()), (row_min_bloc
         dst[NHP + k] = mk<T>(zk.y + zm.y, zm.x - zk.x);
       };
       if constexpr (WAVE) {
-        // each wave unpacks the fields it transformed
+        // Each wave unpacks the fields it transformed, field by field: the
+        // field and its output row are wave-uniform (scalar registers), so an
+        // element costs its two LDS addresses and the store offset.  The flux
+        // pass at N <= 256 (at most two 64-wide sweeps of a field) also
+        // unrolls the sweeps, keeping the LDS addresses in registers across
+        // row pairs; elsewhere that would cost occupancy.
         constexpr int W = NT / 64;
-        const int wv = tid >> 6;
-        // The flux pass at N <= 256 (at most two 64-wide sweeps of a field)
-        // unpacks field by field with the sweeps unrolled: the field, its
-        // output row and the LDS addresses are then wave-uniform or stay in
-        // registers across row pairs.  Elsewhere that costs occupancy, and
-        // the flattened (field, k) walk is kept.
         constexpr int KIT = (NH + 63) / 64;
-        if constexpr (MODE == RM_XB && KIT <= 2) {
-          cx<T>* const row_out = reinterpret_cast<cx<T>*>(out0) + row0 * NHP;
-          for (int fl = 0; fl < seqs_per_wave<NB, NT>(); ++fl) {
-            const int fld = fl * W + wv;
-            if (fld >= nout) break;
-            cx<T>* const dst = row_out + fld * ost;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+        cx<T>* const row_out = reinterpret_cast<cx<T>*>(out0) + row0 * NHP;
+#pragma unroll 1
+        for (int fl = 0; fl < seqs_per_wave<NB, NT>(); ++fl) {
+          const int fld = fl * W + wv;
+          if (fld >= nout) break;
+          cx<T>* const dst = row_out + fld * ost;
+          if constexpr (MODE == RM_XB && KIT <= 2) {
 #pragma unroll
             for (int it = 0; it < KIT; ++it) {
               const int k = (tid & 63) + 64 * it;
               if ((it + 1) * 64 <= NH || k < NH) unpack_row(dst, fld, k);
             }
-          }
-        } else {
-          for (int e = tid & 63; e < seqs_per_wave<NB, NT>() * NH; e += 64) {
-            const int fl = e / NH;
-            const int fld = fl * W + wv;
-            if (fld < nout) unpack(fld, e - fl * NH);
+          } else {
+#pragma unroll 1
+            for (int k = tid & 63; k < NH; k += 64) unpack_row(dst, fld, k);
           }
         }
       } else {

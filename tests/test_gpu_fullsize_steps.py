@@ -20,6 +20,9 @@ the wave-mapped row passes, the graph-replayed AB2 step).
 * A well-conditioned state (compressive m, modest background pressure)
   holds every field of the RHS, R_rho and R_E included, to the flat bars
   (FP32 1e-5, mixed 1e-3) at sizes the oracle runs directly.
+* At 1024^3 (no FP64 build fits), the Euler start and the first AB2 step
+  from the same trigonometric state against the exact RHS and the library's
+  own pure RHS of the stepped state, on the low modes.
 """
 import json
 import os
@@ -191,3 +194,57 @@ def test_rhs_well_conditioned_flat_bars(n, prec):
     errs = per_field_rel_l2(got, ref)
     log("  err", ["%.2e" % e for e in errs])
     assert max(errs) <= BAR[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_euler_and_ab2_steps_at_1024(prec):
+    """The step epilogue at 1024^3 (the 1024^3 bench line's launch shapes:
+    the state / history prefetch of the z-RHS pass, the graph-replayed AB2
+    step), where no FP64 build fits: from the degree-1 trigonometric state,
+    the Euler start must give (U1 - U0)/dt = R0 on the low modes |k_i| <= 4,
+    with R0 exact (the oracle's 16^3 coefficients); the next step must give
+    (U2 - U1)/dt = 1.5 R(U1) - 0.5 R0 with R(U1) the library's own pure
+    right-hand side of the stepped state.  Both hold for any dt.  The
+    difference quotient amplifies the rounding of the stored states by
+    |U| / (dt |R|) (|U| ~ 5, |R| ~ 0.5 here), so the test takes a large step,
+    dt = 0.1 (two explicit steps from a low-mode state stay finite), which
+    leaves the rounding of the working precision, amplified ~100x, below the
+    RHS bars: FP32 1e-5, mixed 1e-3."""
+    n = 1024
+    log(f"[fullsize steps 1024] prec={prec}")
+    gamma, nu, eta, dt = 5.0 / 3.0, 2e-3, 3e-3, 0.1
+    ts = I.trig_state(3)
+    F, _, _ = varying_density_rhs(16, ts, gamma, nu, eta)
+    idx = np.r_[-4:5] % 16
+    R0 = F[:, idx[:, None, None], idx[None, :, None], idx[None, None, :]]   # [f][kz][ky][kx]
+    xs = torch.arange(n, device="cuda:0", dtype=torch.float64) * (2 * np.pi / n)
+    U0 = torch.empty((8, n, n, n), dtype=torch.float32, device="cuda:0")
+    for zi in range(0, n, 64):
+        U0[:, zi:zi + 64] = ts.conserved(xs[zi:zi + 64, None, None], xs[None, :, None], xs[None, None, :], gamma,
+                                         xp=torch).to(torch.float32)
+    S = solver(n, prec, gamma=gamma, nu=nu, eta=eta, dt=dt)
+    try:
+        S.set_state(U0)
+        del U0
+
+        def low_of(t):
+            out = low_mode_coefficients(t, 4).cpu().numpy()
+            del t
+            return out
+
+        L0 = low_of(S.get_state(torch.float32))
+        S.step(1)  # Euler start
+        L1 = low_of(S.get_state(torch.float32))
+        R1 = low_of(S.rhs(S.get_state(torch.float32)))
+        S.step(1)  # first AB2 step
+        L2 = low_of(S.get_state(torch.float32))
+    finally:
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    e1 = [np.linalg.norm((L1[f] - L0[f]) / dt - R0[f]) / np.linalg.norm(R0[f]) for f in range(8)]
+    want2 = 1.5 * R1 - 0.5 * R0
+    e2 = [np.linalg.norm((L2[f] - L1[f]) / dt - want2[f]) / np.linalg.norm(want2[f]) for f in range(8)]
+    log("  Euler start", ["%.2e" % e for e in e1])
+    log("  AB2 step", ["%.2e" % e for e in e2])
+    assert max(e1) <= BAR[prec] and max(e2) <= BAR[prec]
