@@ -25,8 +25,10 @@ def compact_from_full(F):
 
 
 def pitch(n):
-    K = (n - 1) // 3
-    return (K + 1 + 7) // 8 * 8
+    """The library's kx pitch of the compact spectrum (K+1 padded)."""
+    from paper_1810_12707_amd.mhd import mhd_spectrum_pitch
+
+    return mhd_spectrum_pitch(n)
 
 
 def compact_from_flat(a, n):

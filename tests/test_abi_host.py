@@ -57,13 +57,14 @@ def test_workspace_sizing(M):
         return M.mhd_workspace_bytes(M.make_params(n, prec))
 
     # grows like n^3 (the kx padding weighs on small n) and doubles (to within the small fixed parts) from FP32 to FP64
-    assert ws(128, M.MHD_FP32) > 7 * ws(64, M.MHD_FP32)
+    assert ws(256, M.MHD_FP32) > 7 * ws(128, M.MHD_FP32)
     r = ws(128, M.MHD_FP64) / ws(128, M.MHD_FP32)
     assert 1.9 < r < 2.01
     # 512^3 FP32 with all fields resident fits easily in one MI355X (288 GB)
     assert ws(512, M.MHD_FP32) < 20e9
     assert ws(1024, M.MHD_FP32) < 150e9
-    assert M.mhd_spectrum_pitch(32) == 16 and M.mhd_spectrum_pitch(512) == 176
+    # the kx pitch: K+1 rounded up to a multiple of 8 (64-byte FP32 rows)
+    assert [M.mhd_spectrum_pitch(n) for n in (32, 64, 256, 512, 1024)] == [16, 24, 88, 176, 344]
     assert M.mhd_spectrum_size(32) == 21 * 21 * 16
 
 
