@@ -42,11 +42,13 @@ template <typename T, int N> constexpr int col_width() {
 // the state and history), so it wants many resident waves: FP32 at N >= 256
 // runs one first-pass butterfly per thread, which keeps registers low -- 512
 // threads on 16 columns at N = 256, 1024 threads on 16 columns at N = 512
-// (whole 128-byte row segments; 3% faster than 512 threads on 8), 512
-// threads on 8 columns above and for the mixed path.
+// (whole 128-byte row segments; 3% faster than 512 threads on 8), 1024
+// threads on 8 columns at N = 1024 (FP32 228 -> 106 registers, mixed 196 ->
+// 116: four waves per SIMD instead of two, 28.0 -> 21.4 and 35.4 -> 24.0 ms
+// per step), and 512 threads on 8 columns for the mixed path below that.
 template <typename T, int N, bool MX> constexpr bool rhs_wide() { return sizeof(T) == 4 && N >= 256; }
 template <typename T, int N, bool MX> constexpr int rhs_threads() {
-  if (sizeof(T) == 4 && !MX && N == 512) return 4 * kThreads;
+  if (sizeof(T) == 4 && ((!MX && N == 512) || N == 1024)) return 4 * kThreads;
   return rhs_wide<T, N, MX>() ? 2 * kThreads : kThreads;
 }
 template <typename T, int N, bool MX> constexpr int rhs_tile() {
@@ -64,14 +66,16 @@ template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs
 // butterflies.  Measured per pass class: one butterfly per thread (fewer
 // registers, more resident waves) pays for the inverse passes at N = 256 and
 // 512 and for the forward passes at N = 512; the forward passes at N = 256
-// run best with two.  Above 512 (LDS-limited to one
-// workgroup per CU) 512 threads on 8 columns avoid register spills.  The
-// MFMA variant follows the same rule from N = 512 up and for the three-term
-// pass at 256, and keeps 256 threads otherwise (measured).
+// run best with two.  At N = 1024 the passes take 8-column tiles with 1024
+// threads, one first-pass butterfly each (98-126 registers, four waves per
+// SIMD; with 512 threads they held 162-222 and ran two: 8-15% slower per
+// pass, FP32 and mixed).  The MFMA variant follows the FP32 rule from N = 512
+// up and for the three-term pass at 256, and keeps 256 threads otherwise
+// (measured).
 template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
   if (sizeof(T) != 4 || (MX && N < 256) || (MX && N == 256 && MAXT == 1)) return kThreads;
   if (N == 256) return (MAXT > 1 || S > 0) ? 2 * kThreads : kThreads;
-  if (N == 512) return 4 * kThreads;
+  if (N == 512 || N == 1024) return 4 * kThreads;
   return N > 512 ? 2 * kThreads : kThreads;
 }
 template <typename T, int N, bool MX> constexpr int col_tile() {
