@@ -46,8 +46,12 @@ template <typename T, int N> constexpr int col_width() {
 // threads on 8 columns at N = 1024 (FP32 228 -> 106 registers, mixed 196 ->
 // 116: four waves per SIMD instead of two, 28.0 -> 21.4 and 35.4 -> 24.0 ms
 // per step), and 512 threads on 8 columns for the mixed path below that.
+// FP64 at N = 512 takes 512 threads on its 8-column tiles, one butterfly
+// each (146 registers instead of 256 with 256 threads, three waves per SIMD
+// instead of one: 6.89 -> 4.35 ms per step).
 template <typename T, int N, bool MX> constexpr bool rhs_wide() { return sizeof(T) == 4 && N >= 256; }
 template <typename T, int N, bool MX> constexpr int rhs_threads() {
+  if (sizeof(T) == 8 && N == 512) return 2 * kThreads;
   if (sizeof(T) == 4 && ((!MX && N == 512) || N == 1024)) return 4 * kThreads;
   return rhs_wide<T, N, MX>() ? 2 * kThreads : kThreads;
 }
@@ -56,7 +60,9 @@ template <typename T, int N, bool MX> constexpr int rhs_tile() {
   return rhs_wide<T, N, MX>() ? (N == 256 ? 16 : 8) : col_width<T, N>();
 }
 // Minimum resident waves per SIMD asked of the compiler (register cap).
-template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs_wide<T, N, MX>() ? 1 : 3; }
+template <typename T, int N, bool MX> constexpr int rhs_min_waves() {
+  return rhs_wide<T, N, MX>() || (sizeof(T) == 8 && N == 512) ? 1 : 3;
+}
 
 // Threads and tile width of the column passes (S = +1 inverse, -1 forward;
 // MAXT input terms per element).  Long FP32 columns take 16-column tiles, so
@@ -69,10 +75,14 @@ template <typename T, int N, bool MX> constexpr int rhs_min_waves() { return rhs
 // run best with two.  At N = 1024 the passes take 8-column tiles with 1024
 // threads, one first-pass butterfly each (98-126 registers, four waves per
 // SIMD; with 512 threads they held 162-222 and ran two: 8-15% slower per
-// pass, FP32 and mixed).  The MFMA variant follows the FP32 rule from N = 512
+// pass, FP32 and mixed).  FP64 at N = 512 (8-column tiles) takes 512 threads,
+// one butterfly each (144-202 registers instead of 242-256 and one wave per
+// SIMD with 256 threads; the three-term pass 3.02 -> 2.38 ms per step), other
+// FP64 sizes 256.  The MFMA variant follows the FP32 rule from N = 512
 // up and for the three-term pass at 256, and keeps 256 threads otherwise
 // (measured).
 template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
+  if (sizeof(T) == 8 && N == 512) return 2 * kThreads;
   if (sizeof(T) != 4 || (MX && N < 256) || (MX && N == 256 && MAXT == 1)) return kThreads;
   if (N == 256) return (MAXT > 1 || S > 0) ? 2 * kThreads : kThreads;
   if (N == 512 || N == 1024) return 4 * kThreads;
@@ -582,8 +592,11 @@ __device__ __forceinline__ void flush_status(double cfl, int bad, double* slots,
 // of two (13% faster at 512) or three (3% at 256).  The FP32 velocity pass at
 // N = 256 takes 128: two waves of two fields each, whose 32-butterfly radix-8
 // passes then fill every lane (256 threads left half of them idle; 19%).
+// The FP64 flux pass at N = 512 takes 512 too (its 156 KB LDS tile allows
+// one workgroup per CU: two waves per SIMD instead of one, 6.78 -> 5.63 ms).
 template <typename T, int N, int MODE, bool MX> constexpr int row_threads() {
   if (sizeof(T) == 4 && !MX && MODE == RM_XB && (N == 512 || N == 256)) return 2 * kThreads;
+  if (sizeof(T) == 8 && MODE == RM_XB && N == 512) return 2 * kThreads;
   if (sizeof(T) == 4 && !MX && MODE == RM_XA && N == 256) return kThreads / 2;
   return (sizeof(T) == 4 && N >= 1024) ? 2 * kThreads : kThreads;
 }
