@@ -78,12 +78,12 @@ template <typename T, int N, bool MX> constexpr int rhs_min_waves() {
 // pass, FP32 and mixed).  FP64 at N = 512 (8-column tiles) takes 512 threads,
 // one butterfly each (144-202 registers instead of 242-256 and one wave per
 // SIMD with 256 threads; the three-term pass 3.02 -> 2.38 ms per step), other
-// FP64 sizes 256.  The MFMA variant follows the FP32 rule from N = 512
-// up and for the three-term pass at 256, and keeps 256 threads otherwise
-// (measured).
+// FP64 sizes 256.  The MFMA variant follows the FP32 rule from N = 256 up
+// (its one-term inverse passes at 256 hold 112 registers with 512 threads,
+// 180 with 256: 8-12% faster) and keeps 256 threads below.
 template <typename T, int N, bool MX, int S, int MAXT> constexpr int col_threads() {
   if (sizeof(T) == 8 && N == 512) return 2 * kThreads;
-  if (sizeof(T) != 4 || (MX && N < 256) || (MX && N == 256 && MAXT == 1)) return kThreads;
+  if (sizeof(T) != 4 || (MX && N < 256)) return kThreads;
   if (N == 256) return (MAXT > 1 || S > 0) ? 2 * kThreads : kThreads;
   if (N == 512 || N == 1024) return 4 * kThreads;
   return N > 512 ? 2 * kThreads : kThreads;
