@@ -355,14 +355,14 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
     return f * sc + (int64_t)l * LS + col;
   };
   // The state (for the update, and B^ for the resistive term) and the
-  // previous RHS: on the wide shapes -- FP32 from N = 512, mixed at 512 --
-  // they are loaded before the transforms, so that these loads are in flight
-  // while the flux groups are transformed (5% and 14% faster).  FP32 at
-  // N = 256 (a resident workgroup lost to registers, 4% slower), mixed at 256
-  // (139 -> 108 registers without it: two workgroups per CU instead of one,
-  // 0.458 -> 0.372 ms) and at 1024 (18% slower) load them last, as do the
-  // narrow shapes.
-  constexpr bool PRE = rhs_wide<T, N, MX>() && (MX ? N == 512 : N >= 512);
+  // previous RHS: FP32 from N = 512 loads them before the transforms, so that
+  // these loads are in flight while the flux groups are transformed (5%
+  // faster).  FP32 at N = 256 (a resident workgroup lost to registers, 4%
+  // slower), the mixed path (its MFMA stage needs the registers: 139-140 ->
+  // 108 without the early loads, two workgroups per CU instead of one,
+  // 0.458 -> 0.372 ms at 256, 3.35 -> 2.59 ms at 512) and the narrow shapes
+  // load them last.
+  constexpr bool PRE = rhs_wide<T, N, MX>() && !MX && N >= 512;
   const bool need_state = !rout || (f >= 4 && f <= 6);
   const bool need_prev = !rout && use_prev;
   cx<T> u_pre[LP::CNT][LP::R], r_pre[LP::CNT][LP::R];
