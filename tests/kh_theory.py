@@ -55,3 +55,60 @@ def growth_rate(k: float, n: int = 160) -> float:
     c = wave_speeds(k, n)
     c = c[np.isfinite(c)]
     return float(k * np.max(c.imag))
+
+
+def viscous_wave_speeds(k: float, re: float, n: int = 160, L: float = 2.0) -> np.ndarray:
+    """Eigenvalues c of the Orr-Sommerfeld equation for U = tanh(y) at
+    wavenumber k and Reynolds number re = U0 d / nu,
+
+        (U - c) (D2 - k^2) phi - U'' phi = (D2 - k^2)^2 phi / (i k re),
+
+    on the same mapped collocation grid, phi = 0 at y = +-infinity (the
+    decaying eigenfunctions also have vanishing derivatives there, which
+    the algebraic map imposes to all orders)."""
+    xi, D = _cheb(n)
+    xi, D = xi[1:-1], D[1:-1, 1:-1]
+    s = np.sqrt(1.0 - xi * xi)
+    y = L * xi / s
+    Dy = (s ** 3 / L)[:, None] * D
+    D2 = Dy @ Dy
+    U = np.tanh(y)
+    Upp = -2.0 * U * (1.0 - U * U)
+    K = D2 - k * k * np.eye(len(y))
+    A = U[:, None] * K - np.diag(Upp) - (K @ K) / (1j * k * re)
+    return scipy.linalg.eigvals(A, K)
+
+
+def viscous_growth_rate(k: float, re: float, n: int = 160) -> float:
+    """Temporal growth rate k Im(c) (units U0 / d) of the Orr-Sommerfeld
+    mode that continues the inviscid unstable mode (the eigenvalue nearest
+    to it)."""
+    c0 = wave_speeds(k, n)
+    c0 = c0[np.isfinite(c0)]
+    ci = c0[np.argmax(c0.imag)]
+    c = viscous_wave_speeds(k, re, n)
+    c = c[np.isfinite(c)]
+    return float(k * c[np.argmin(np.abs(c - ci))].imag)
+
+
+def unstable_mode(k: float, n: int = 200, L: float = 2.0):
+    """The unstable Rayleigh mode at wavenumber k: its wave speed c, the
+    collocation points y (increasing) and phi, phi' there, normalised to
+    max |phi| = 1 (stream function phi(y) exp(i k x))."""
+    xi, D = _cheb(n)
+    xi, D = xi[1:-1], D[1:-1, 1:-1]
+    s = np.sqrt(1.0 - xi * xi)
+    y = L * xi / s
+    Dy = (s ** 3 / L)[:, None] * D
+    D2 = Dy @ Dy
+    U = np.tanh(y)
+    Upp = -2.0 * U * (1.0 - U * U)
+    K = D2 - k * k * np.eye(len(y))
+    A = U[:, None] * K - np.diag(Upp)
+    w, V = scipy.linalg.eig(A, K)
+    w = np.where(np.isfinite(w), w, 0.0)
+    j = int(np.argmax(w.imag))
+    phi = V[:, j] / V[np.argmax(np.abs(V[:, j])), j]
+    dphi = Dy @ phi
+    order = np.argsort(y)
+    return w[j], y[order], phi[order], dphi[order]
