@@ -53,3 +53,15 @@ def test_fastest_growing_mode_matches_the_literature():
 @pytest.mark.parametrize("k", [0.2223, 0.4446, 0.6669])
 def test_converged_in_the_collocation_points(k):
     assert abs(K.growth_rate(k, 160) - K.growth_rate(k, 240)) <= 1e-8
+
+
+@pytest.mark.parametrize("k", [0.2223, 0.6669])
+def test_viscous_rates_reduce_to_rayleigh_and_converge(k):
+    """The Orr-Sommerfeld rate the GPU test uses: it tends to the (pinned)
+    inviscid rate as Re grows, decreases as viscosity rises, and is
+    converged in the collocation points at the test's Re."""
+    inv = K.growth_rate(k)
+    assert abs(K.viscous_growth_rate(k, 1e7) - inv) <= 1e-5 * inv  # an O(1 / Re) correction
+    rates = [K.viscous_growth_rate(k, re) for re in (300.0, 1000.0, 2223.0, 1e5)]
+    assert all(a < b for a, b in zip(rates, rates[1:])) and rates[-1] < inv
+    assert abs(K.viscous_growth_rate(k, 2223.0, 160) - K.viscous_growth_rate(k, 2223.0, 240)) <= 1e-8
