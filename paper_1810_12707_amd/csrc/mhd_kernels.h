@@ -101,27 +101,6 @@ __device__ __forceinline__ void st(T* base, int64_t idx, cx<T> v) {
   reinterpret_cast<cx<T>*>(base)[idx] = v;
 }
 
-// sum_t coef_t * (i k_axis or 1) * in[src_t][idx]
-template <typename T>
-__device__ __forceinline__ cx<T> combine(const OutSpec& sp, const T* const* in, int64_t idx, int kx, int ky, int kz) {
-  cx<T> acc = mk<T>(0, 0);
-  for (int t = 0; t < sp.nterms; ++t) {
-    const Term& tm = sp.t[t];
-    cx<T> v = ld(in[tm.src], idx);
-    T c = T(tm.coef);
-    if (tm.axis < 0) {
-      acc.x += c * v.x;
-      acc.y += c * v.y;
-    } else {
-      const T k = T(tm.axis == 0 ? kx : (tm.axis == 1 ? ky : kz));
-      const T ck = c * k;  // (c * i k) * v
-      acc.x -= ck * v.y;
-      acc.y += ck * v.x;
-    }
-  }
-  return acc;
-}
-
 template <typename T, int N, int NT = kThreads>
 __device__ __forceinline__ void load_twiddles(cx<T>* stw, const T* tw, int tid) {
   for (int i = tid; i < N; i += NT) stw[i] = ld(tw, i);
@@ -198,7 +177,13 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
   // raw first-pass loads of one item, one set per input term
   cx<T> px[MAXT][FP::CNT][FP::R];
   auto issue = [&](const Item& it) {
+    // the item's input pointers, once per item (uniform: scalar registers)
+    // rather than once per element under the element's predicate
     const OutSpec& sp = a.spec[it.f];
+    const int nt = sp.nterms;
+    const T* src[MAXT];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) src[t] = member_ptr(a.in[t < nt ? sp.t[t].src : 0], it.m, a.bt.mstride);
     const int64_t base_in = it.outer * os_in + it.c0;
 #pragma unroll
     for (int i = 0; i < FP::CNT; ++i) {
@@ -219,7 +204,7 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
           const int64_t idx = base_in + l * ls_in + c;
 #pragma unroll
           for (int t = 0; t < MAXT; ++t)
-            if (t < sp.nterms) px[t][i][r] = ld(member_ptr(a.in[sp.t[t].src], it.m, a.bt.mstride), idx);
+            if (t < nt) px[t][i][r] = ld(src[t], idx);
         }
       }
     }
@@ -230,7 +215,16 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
   if (item >= 0) issue(decode(item));
   for (int k = 0; item >= 0; ++k) {
     const Item it = decode(item);
+    // the item's multipliers, once per item
     const OutSpec& sp = a.spec[it.f];
+    const int nt = sp.nterms;
+    T cf[MAXT];
+    int ax[MAXT];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      cf[t] = t < nt ? T(sp.t[t].coef) : T(0);
+      ax[t] = t < nt ? sp.t[t].axis : -1;
+    }
     // combine the prefetched terms with their spectral multipliers
     cx<T> v[FP::CNT][FP::R];
 #pragma unroll
@@ -260,15 +254,13 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
           }
 #pragma unroll
           for (int t = 0; t < MAXT; ++t) {
-            if (t < sp.nterms) {
-              const Term& tm = sp.t[t];
-              const T cf = T(tm.coef);
+            if (t < nt) {
               const cx<T> xv = px[t][i][r];
-              if (tm.axis < 0) {
-                acc.x += cf * xv.x;
-                acc.y += cf * xv.y;
+              if (ax[t] < 0) {
+                acc.x += cf[t] * xv.x;
+                acc.y += cf[t] * xv.y;
               } else {
-                const T ck = cf * T(tm.axis == 0 ? kx : (tm.axis == 1 ? kyy : kz));
+                const T ck = cf[t] * T(ax[t] == 0 ? kx : (ax[t] == 1 ? kyy : kz));
                 acc.x -= ck * xv.y;
                 acc.y += ck * xv.x;
               }
@@ -410,6 +402,14 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
     if (grp == 1) __syncthreads();   // the LDS tile is about to be rewritten
     const T* p0 = member_ptr(a.flux[sp.t[0].src], mem, ms);
     const T* p1 = nt > 1 ? member_ptr(a.flux[sp.t[1].src], mem, ms) : p0;
+    // the multipliers, converted once per group rather than once per element
+    T cf[2];
+    int ax[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      cf[t] = t < nt ? T(sp.t[t].coef) : T(0);
+      ax[t] = t < nt ? sp.t[t].axis : -1;
+    }
     auto load = [&](int c, int q) -> cx<T> {
       const int col = c0 + c;
       cx<T> v = mk<T>(0, 0);
@@ -423,13 +423,11 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         if (t < nt) {
-          const Term& tm = sp.t[t];
-          const T cf = T(tm.coef);
-          if (tm.axis < 0) {
-            v.x += cf * xs[t].x;
-            v.y += cf * xs[t].y;
+          if (ax[t] < 0) {
+            v.x += cf[t] * xs[t].x;
+            v.y += cf[t] * xs[t].y;
           } else {
-            const T ck = cf * T(tm.axis == 0 ? kx : ky);
+            const T ck = cf[t] * T(ax[t] == 0 ? kx : ky);
             v.x -= ck * xs[t].y;
             v.y += ck * xs[t].x;
           }
