@@ -217,11 +217,12 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
     const Item it = decode(item);
     // the item's multipliers, once per item
     const OutSpec& sp = a.spec[it.f];
-    // Each term is re * x or dk * (i k_axis) * x.  The three-term pass sets
-    // the factor that does not apply to zero and combines without a branch
-    // per element (absent terms have both zero and zeroed prefetch
-    // registers): 4.6% faster at 512.  The one-term passes keep the branch
-    // on the term's kind (uniform), which measured faster there.
+    // Each term is re * x or dk * (i k_axis) * x.  The three-term pass and
+    // the mixed path set the factor that does not apply to zero and combine
+    // without a branch per element (absent terms have both zero and zeroed
+    // prefetch registers): 4.6% faster for the three-term pass at 512.  The
+    // FP32 and FP64 one-term passes keep the branch on the term's kind
+    // (uniform), which measured faster there.
     const int nt = sp.nterms;
     T re[MAXT], dk[MAXT];
     int ax[MAXT];
@@ -263,7 +264,7 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
 #pragma unroll
           for (int t = 0; t < MAXT; ++t) {
             const cx<T> xv = px[t][i][r];
-            if constexpr (MAXT > 1) {
+            if constexpr (MAXT > 1 || MX) {
               const T ck = dk[t] * T(ax[t] == 1 ? kyy : (ax[t] == 2 ? kz : kx));
               acc.x += re[t] * xv.x;
               acc.x -= ck * xv.y;
@@ -436,7 +437,16 @@ __global__ void __launch_bounds__((rhs_threads<T, N, MX>()), (rhs_min_waves<T, N
       const cx<T> xs[2] = {x0, x1};
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        if (t < nt) {
+        if constexpr (MX) {
+          // branch-free, as in the column passes (faster on the mixed path
+          // only): absent terms have zero factors and a zero second input
+          const T re = ax[t] < 0 ? cf[t] : T(0);
+          const T ck = (ax[t] < 0 ? T(0) : cf[t]) * T(ax[t] == 1 ? ky : kx);
+          v.x += re * xs[t].x;
+          v.x -= ck * xs[t].y;
+          v.y += re * xs[t].y;
+          v.y += ck * xs[t].x;
+        } else if (t < nt) {
           if (ax[t] < 0) {
             v.x += cf[t] * xs[t].x;
             v.y += cf[t] * xs[t].y;
