@@ -10,28 +10,39 @@
 namespace mhd {
 namespace {
 
+// Column passes: one instantiation per direction, term count and axis (z or y).
+template <typename T, int N, int S, int MAXT, bool MX>
+void col_launch(const ColArgs<T>& a, dim3 g, hipStream_t s) {
+  constexpr int nt = col_threads<T, N, MX, S, MAXT>();
+  if (a.kind == PK_ZINV || a.kind == PK_ZFWD) hipLaunchKernelGGL((k_col<T, N, S, MAXT, MX, true>), g, dim3(nt), 0, s, a);
+  else hipLaunchKernelGGL((k_col<T, N, S, MAXT, MX, false>), g, dim3(nt), 0, s, a);
+}
 template <typename T, int N, bool MX>
 void col_inv(int maxt, const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  if (maxt <= 1) hipLaunchKernelGGL((k_col<T, N, 1, 1, MX>), g, dim3(col_threads<T, N, MX, 1, 1>()), 0, s, a);
-  else hipLaunchKernelGGL((k_col<T, N, 1, kMaxTerms, MX>), g, dim3(col_threads<T, N, MX, 1, kMaxTerms>()), 0, s, a);
+  if (maxt <= 1) col_launch<T, N, 1, 1, MX>(a, g, s);
+  else col_launch<T, N, 1, kMaxTerms, MX>(a, g, s);
 }
 template <typename T, int N, bool MX>
 void col_fwd(const ColArgs<T>& a, dim3 g, hipStream_t s) {
-  hipLaunchKernelGGL((k_col<T, N, -1, 1, MX>), g, dim3(col_threads<T, N, MX, -1, 1>()), 0, s, a);
+  col_launch<T, N, -1, 1, MX>(a, g, s);
+}
+// Resident workgroups per CU of a column-pass class: the smaller of its z and
+// y instantiations (the persistent grid is sized once per class).
+template <typename T, int N, int S, int MAXT, bool MX>
+int col_occ(void) {
+  constexpr int nt = col_threads<T, N, MX, S, MAXT>();
+  int bz = 0, by = 0;
+  const hipError_t ez = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bz, k_col<T, N, S, MAXT, MX, true>, nt, 0);
+  const hipError_t ey = hipOccupancyMaxActiveBlocksPerMultiprocessor(&by, k_col<T, N, S, MAXT, MX, false>, nt, 0);
+  if (ez != hipSuccess || ey != hipSuccess) return 1;
+  const int b = bz < by ? bz : by;
+  return b > 0 ? b : 1;
 }
 template <typename T, int N, bool MX>
 int col_occupancy(int dir, int maxt) {
-  int blocks = 0;
-  hipError_t e;
-  if (dir < 0)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, -1, 1, MX>, col_threads<T, N, MX, -1, 1>(),
-                                                     0);
-  else if (maxt <= 1)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, 1, MX>, col_threads<T, N, MX, 1, 1>(), 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_col<T, N, 1, kMaxTerms, MX>,
-                                                     col_threads<T, N, MX, 1, kMaxTerms>(), 0);
-  return (e == hipSuccess && blocks > 0) ? blocks : 1;
+  if (dir < 0) return col_occ<T, N, -1, 1, MX>();
+  if (maxt <= 1) return col_occ<T, N, 1, 1, MX>();
+  return col_occ<T, N, 1, kMaxTerms, MX>();
 }
 template <typename T, int N, bool MX>
 void rhs(const RhsArgs<T>& a, dim3 g, hipStream_t s) {

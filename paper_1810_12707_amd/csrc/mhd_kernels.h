@@ -133,7 +133,10 @@ __device__ __forceinline__ TileField tile_field(int nfields) {
 // that were loaded from HBM while the previous item was being transformed
 // (up to MAXT input terms per element; the zero gap of a band input is never
 // loaded); the last pass stores straight to HBM (dropped modes skipped).
-template <typename T, int N, int S, int MAXT, bool MX>
+// Z: a z pass (else a y pass), fixed at compile time so that the column
+// geometry, the strides and the wavenumbers of the multipliers are constants
+// rather than uniform branches per element.
+template <typename T, int N, int S, int MAXT, bool MX, bool Z>
 __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(const ColArgs<T> a) {
   using PL = PlanOf<N, MX>;
   constexpr int C = col_tile<T, N, MX>();
@@ -143,21 +146,20 @@ __global__ void __launch_bounds__((col_threads<T, N, MX, S, MAXT>())) k_col(cons
   __shared__ cx<T> tile[N * C];
   __shared__ cx<T> stw[N];
   const int tid = threadIdx.x;
-  const bool zpass = (a.kind == PK_ZINV || a.kind == PK_ZFWD);
+  constexpr bool zpass = Z;
   // z passes: columns are (ky, kx) flattened over the padded pitch; padding
   // columns (kx >= NH) are never read or written
-  const int ncols = zpass ? NBB * NHP : NH;
-  const int ntiles = (ncols + C - 1) / C;
+  constexpr int ncols = zpass ? NBB * NHP : NH;
+  constexpr int ntiles = (ncols + C - 1) / C;
   const int per_mem = ntiles * (zpass ? 1 : N) * a.nout;
   const int total = per_mem * a.bt.nmem;  // < 2^31 for every supported size and member count
-  // strides (complex elements) of the input and output layouts
-  int64_t os_in, ls_in, os_out, ls_out;
-  switch (a.kind) {
-    case PK_ZINV: os_in = 0; ls_in = NBB * NHP; os_out = 0; ls_out = NBB * NHP; break;
-    case PK_YINV: os_in = (int64_t)NBB * NHP; ls_in = NHP; os_out = (int64_t)N * NHP; ls_out = NHP; break;
-    case PK_YFWD: os_in = (int64_t)N * NHP; ls_in = NHP; os_out = (int64_t)NBB * NHP; ls_out = NHP; break;
-    default: os_in = 0; ls_in = NBB * NHP; os_out = 0; ls_out = NBB * NHP; break;
-  }
+  // strides (complex elements) of the input and output layouts: z passes
+  // (either direction) map [kz][ky][kx] onto itself; the inverse y pass reads
+  // [kz][ky band][kx] and writes [kz][y][kx], the forward one the reverse
+  constexpr int64_t os_in = zpass ? 0 : (S > 0 ? (int64_t)NBB * NHP : (int64_t)N * NHP);
+  constexpr int64_t ls_in = zpass ? (int64_t)NBB * NHP : NHP;
+  constexpr int64_t os_out = zpass ? 0 : (S > 0 ? (int64_t)N * NHP : (int64_t)NBB * NHP);
+  constexpr int64_t ls_out = ls_in;
   load_twiddles<T, N, NT>(stw, a.tw, tid);
   auto col_ok = [&](int col) { return col < ncols && (!zpass || col - (col / NHP) * NHP < NH); };
 

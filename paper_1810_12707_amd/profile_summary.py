@@ -97,11 +97,11 @@ def per_kernel_kib(path: str, counter: str) -> dict:
 # Launch classes of one step in launch order, with the kernel each uses
 # ({mx}: false on the FP32 path, true on the mixed path).
 STEP_SEQUENCE = [
-    ("zinv_a", "k_col<float, {n}, 1, 1, {mx}>"), ("yinv_a", "k_col<float, {n}, 1, 1, {mx}>"),
-    ("xa", "k_row<float, {n}, 0, {mx}>"), ("yfwd_a", "k_col<float, {n}, -1, 1, {mx}>"),
-    ("zfwd_a", "k_col<float, {n}, -1, 1, {mx}>"), ("zinv_b", "k_col<float, {n}, 1, 3, {mx}>"),
-    ("yinv_b", "k_col<float, {n}, 1, 1, {mx}>"), ("xb", "k_row<float, {n}, 1, {mx}>"),
-    ("yfwd_b", "k_col<float, {n}, -1, 1, {mx}>"), ("rho", "k_rho_rhs<float>"), ("zrhs", "k_zfwd_rhs<float, {n}, {mx}>"),
+    ("zinv_a", "k_col<float, {n}, 1, 1, {mx}, true>"), ("yinv_a", "k_col<float, {n}, 1, 1, {mx}, false>"),
+    ("xa", "k_row<float, {n}, 0, {mx}>"), ("yfwd_a", "k_col<float, {n}, -1, 1, {mx}, false>"),
+    ("zfwd_a", "k_col<float, {n}, -1, 1, {mx}, true>"), ("zinv_b", "k_col<float, {n}, 1, 3, {mx}, true>"),
+    ("yinv_b", "k_col<float, {n}, 1, 1, {mx}, false>"), ("xb", "k_row<float, {n}, 1, {mx}>"),
+    ("yfwd_b", "k_col<float, {n}, -1, 1, {mx}, false>"), ("rho", "k_rho_rhs<float>"), ("zrhs", "k_zfwd_rhs<float, {n}, {mx}>"),
 ]
 
 

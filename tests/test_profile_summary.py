@@ -11,15 +11,15 @@ HEAD = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "
 
 def kernel_names(n):
     return {
-        "zinv_a": f"void mhd::k_col<float, {n}, 1, 1, false>(mhd::ColArgs<float>)",
-        "yinv_a": f"void mhd::k_col<float, {n}, 1, 1, false>(mhd::ColArgs<float>)",
+        "zinv_a": f"void mhd::k_col<float, {n}, 1, 1, false, true>(mhd::ColArgs<float>)",
+        "yinv_a": f"void mhd::k_col<float, {n}, 1, 1, false, false>(mhd::ColArgs<float>)",
         "xa": f"void mhd::k_row<float, {n}, 0, false>(mhd::RowArgs<float>)",
-        "yfwd_a": f"void mhd::k_col<float, {n}, -1, 1, false>(mhd::ColArgs<float>)",
-        "zfwd_a": f"void mhd::k_col<float, {n}, -1, 1, false>(mhd::ColArgs<float>)",
-        "zinv_b": f"void mhd::k_col<float, {n}, 1, 3, false>(mhd::ColArgs<float>)",
-        "yinv_b": f"void mhd::k_col<float, {n}, 1, 1, false>(mhd::ColArgs<float>)",
+        "yfwd_a": f"void mhd::k_col<float, {n}, -1, 1, false, false>(mhd::ColArgs<float>)",
+        "zfwd_a": f"void mhd::k_col<float, {n}, -1, 1, false, true>(mhd::ColArgs<float>)",
+        "zinv_b": f"void mhd::k_col<float, {n}, 1, 3, false, true>(mhd::ColArgs<float>)",
+        "yinv_b": f"void mhd::k_col<float, {n}, 1, 1, false, false>(mhd::ColArgs<float>)",
         "xb": f"void mhd::k_row<float, {n}, 1, false>(mhd::RowArgs<float>)",
-        "yfwd_b": f"void mhd::k_col<float, {n}, -1, 1, false>(mhd::ColArgs<float>)",
+        "yfwd_b": f"void mhd::k_col<float, {n}, -1, 1, false, false>(mhd::ColArgs<float>)",
         "rho": "void mhd::(anonymous namespace)::k_rho_rhs<float>(mhd::RhsArgs<float>)",
         "zrhs": f"void mhd::k_zfwd_rhs<float, {n}, false>(mhd::RhsArgs<float>)",
     }
