@@ -4,9 +4,12 @@ the GPU, against the linear theory of the tanh shear layer.
 The paper's runs start from tanh shear layers (vorticity omega0 sech^2 of
 the distance to the layer over d) and compare the growth rates of single
 modes with a closed form (Drazin's).  As printed, that formula cannot be
-pinned (see DESIGN), so the growth rates here are held to the linear theory
-of the tanh layer itself: the Orr-Sommerfeld equation at the run's Reynolds
-number, solved in tests/kh_theory.py (whose inviscid limit, Rayleigh's
+pinned (its variables are not made dimensionless consistently, it describes
+a broken-line profile rather than the tanh layers the runs start from, and
+it is stated for twice the growth rate), so the growth rates here are held
+to the linear theory of the tanh layer itself: the Orr-Sommerfeld equation
+at the run's Reynolds number, solved in tests/kh_theory.py (whose inviscid
+limit, Rayleigh's
 equation, tests/test_kh_theory.py pins to its neutral and long-wave closed
 forms and to the tabulated fastest mode).
 
