@@ -9,9 +9,8 @@ a broken-line profile rather than the tanh layers the runs start from, and
 it is stated for twice the growth rate), so the growth rates here are held
 to the linear theory of the tanh layer itself: the Orr-Sommerfeld equation
 at the run's Reynolds number, solved in tests/kh_theory.py (whose inviscid
-limit, Rayleigh's
-equation, tests/test_kh_theory.py pins to its neutral and long-wave closed
-forms and to the tabulated fastest mode).
+limit, Rayleigh's equation, tests/test_kh_theory.py pins to its neutral and
+long-wave closed forms and to the tabulated fastest mode).
 
 Set-up: 256^3 with every field independent of z (quasi-2D), two layers
 u_x = U0 [tanh((y - pi/2)/d) - tanh((y - 3pi/2)/d) - 1], d = 0.2223, so the
